@@ -1,0 +1,247 @@
+/*
+ * m1.h -- C ABI of the MI355X (gfx950) gray M1 radiation step library.
+ *
+ * The library advances the radiation moments (E_r, F_r) of the gray M1
+ * scheme coupled to a static gas: one step is
+ *
+ *   m1_step_explicit   transport of (E, F): PLM van Leer reconstruction with
+ *                      the f-preserving face fix, Levermore closure, HLL
+ *                      fluxes with the optical-depth speed limiter, at the
+ *                      reduced speed of light c_hat, conservative update in
+ *                      Cartesian, cylindrical or spherical coordinates
+ *                      (paper Sect. 2.4-2.7);
+ *   m1_step_implicit   per-cell backward-Euler radiation-matter exchange,
+ *                      the 2x2 system of Eq. implicit_matrix, flux damping of
+ *                      Eq. source_discrete2 and the gas update from the
+ *                      rescaled conservation laws (Sect. 2.7, 2.8).
+ *
+ * Conventions
+ *   - F is the paper's radiation flux that carries the 1/c factor
+ *     (Sect. 2.1), so the reduced flux f = |F|/E lies in [0, 1].
+ *   - Cells are stored as contiguous structure-of-arrays, one array per
+ *     field, index ((k*n1)+j)*n0+i with i along d = 0 (x / R / r), j along
+ *     d = 1 (y / phi / theta), k along d = 2 (z / z / phi).  Vector
+ *     components are in the local orthonormal basis of the grid.
+ *   - Device pointers are HIP device memory owned by the caller, 256-byte
+ *     aligned.  Radiation arrays (E, Fx, Fy, Fz) are double (M1_P64) or
+ *     float (M1_F32); gas arrays (rho, mx, my, mz, Eg) are always double.
+ *   - All work is enqueued asynchronously on the stream given by
+ *     m1_set_stream (default: the null stream); no call synchronises except
+ *     m1_sync, m1_diagnostics, m1_mlp_train and m1_mlp_get.
+ *   - Every function returns an m1_status; a negative value is an error
+ *     whose text m1_last_error() returns.  No call allocates device memory
+ *     after m1_bind_state except m1_set_opacity_table, m1_set_opacity_mlp
+ *     and m1_mlp_train (which own their buffers until m1_destroy).
+ */
+#ifndef M1_H
+#define M1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    M1_OK = 0,
+    M1_EINVAL = -1,   /* bad argument: dimensions, pointers, ranges */
+    M1_ENOMEM = -2,   /* device or host allocation failed */
+    M1_EDEVICE = -3,  /* HIP runtime error (launch or deferred kernel error) */
+    M1_ESTATE = -4,   /* call out of order (e.g. implicit before explicit) */
+    M1_ENOTSUP = -5   /* valid request this build does not implement */
+} m1_status;
+
+typedef enum { M1_CARTESIAN = 0, M1_CYLINDRICAL = 1, M1_SPHERICAL = 2 } m1_geometry;
+typedef enum { M1_BC_PERIODIC = 0, M1_BC_OUTFLOW = 1 } m1_bc;
+typedef enum { M1_P64 = 0, M1_F32 = 1 } m1_precision;
+typedef enum { M1_OPAC_CONSTANT = 0, M1_OPAC_POWERLAW = 1 } m1_opacity_model;
+
+/* Grid: ndim active directions (1..3); n[d] interior cells (n[d] = 1 for an
+ * inactive direction); faces[d] = n[d]+1 strictly increasing coordinates
+ * (host memory, copied).  Spherical: r >= 0 and 0 <= theta <= pi;
+ * cylindrical: R >= 0.  bc[d][0|1] = lower/upper boundary of direction d. */
+typedef struct {
+    int ndim;
+    int n[3];
+    const double *faces[3];
+    int bc[3][2];
+} m1_grid;
+
+/* Physical and numerical parameters (m1_params_default fills them):
+ * c       true speed of light (default: c_hat), enters the gas energy
+ *         exchange (Eq. internal) and the rescaled energy total (Sect. 2.7)
+ * a_rad   radiation constant a_R (default 1)
+ * gamma   adiabatic index; C_v = rho / (gamma - 1) per volume (default 5/3)
+ * precision  M1_P64 (all FP64) or M1_F32 (FP32 radiation storage and
+ *         transport, FP64 implicit solve and gas)
+ * e_floor lower bound enforced on E after transport (default 1e-30) */
+typedef struct {
+    double c;
+    double a_rad;
+    double gamma;
+    int precision;
+    double e_floor;
+} m1_params;
+
+/* Caller-owned device state bound to a context (see conventions). */
+typedef struct {
+    void *E, *Fx, *Fy, *Fz;
+    const double *rho;
+    double *mx, *my, *mz, *Eg;
+} m1_fields;
+
+/* Conserved totals and extrema of the bound state (m1_diagnostics):
+ * rad_energy = sum V E;  total_energy = sum V (E_g + (c/c_hat) E)
+ * momentum[3] = sum V (m + F / c_hat) (meaningful for Cartesian grids)
+ * min_E, max_f over cells; counters of fix-ups since m1_bind_state:
+ * [0] E floor after transport, [1] f <= 1 rescale after transport,
+ * [2] f <= 1 rescale after the implicit step. */
+typedef struct {
+    double rad_energy;
+    double total_energy;
+    double momentum[3];
+    double min_E;
+    double max_f;
+    long long counters[4];
+} m1_diag;
+
+/* MLP opacity surrogate: 2 -> 64 -> 64 -> 2 tanh network with a linear
+ * 2 -> 2 shortcut, inputs x = 2 (l - l_min)/(l_max - l_min) - 1 of the table
+ * coordinates (log10 rho + off_rho, log10 T + off_T) clamped to the bound
+ * table's axes, outputs y with log10 kappa_{P,R} = y * std + mean.
+ * theta: 4486 float32 parameters in the order W1[64][2] b1[64] W2[64][64]
+ * b2[64] W3[2][64] b3[2] Ws[2][2] (host memory, copied). */
+#define M1_MLP_NPARAM 4486
+typedef struct {
+    const float *theta;
+    double norm[4]; /* mean_P, std_P, mean_R, std_R */
+} m1_mlp;
+
+/* Training of the surrogate on the GPU by the library's own kernels against
+ * bilinear lookups of the bound table.  samples: device float32 [n][2] table
+ * coordinates (log10 rho + off, log10 T + off), the first n_train for
+ * training, the remaining n_eval held out.  theta_init: host float32
+ * initial parameters (M1_MLP_NPARAM). */
+typedef struct {
+    const float *samples;
+    long n_train;
+    long n_eval;
+    const float *theta_init;
+    int batch;        /* samples per Adam step (multiple of 64, <= 4096) */
+    long steps;       /* Adam steps */
+    double lr;        /* peak learning rate */
+    double lr_final;  /* learning rate at the last step (cosine decay) */
+    double beta1, beta2, eps;
+} m1_train_cfg;
+
+typedef struct {
+    double final_loss;      /* mean over the last 100 steps */
+    double max_rel_err_P;   /* max |kappa_mlp / kappa_table - 1| on held-out */
+    double max_rel_err_R;
+    double seconds;         /* device time of the training loop */
+} m1_train_report;
+
+typedef struct m1_ctx m1_ctx;
+
+/* Fill *p with defaults for reduced speed of light c_hat. */
+m1_status m1_params_default(double c_hat, m1_params *p);
+
+/* Create a context for grid g (copied) in geometry geom with reduced speed
+ * of light c_hat (> 0).  p may be NULL (defaults).  Uploads the separable
+ * metric arrays of the grid.  Errors: M1_EINVAL (ndim outside 1..3,
+ * n[d] < 1, n[d] != 1 for d >= ndim, non-increasing faces, negative radius,
+ * theta outside [0, pi], c_hat <= 0, unknown enum), M1_ENOMEM, M1_EDEVICE. */
+m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_params *p,
+                    m1_ctx **out);
+
+/* Free the context and every library-owned buffer; never the caller's. */
+m1_status m1_destroy(m1_ctx *ctx);
+
+/* Enqueue all further work on hipStream_t `stream` (NULL: null stream). */
+m1_status m1_set_stream(m1_ctx *ctx, void *stream);
+
+/* Bind caller-owned device arrays (must outlive the binding) and allocate
+ * the library's scratch (transported E*, F*, opacity caches, reduction
+ * buffers).  Evaluates the opacity cache from the current gas state.
+ * M1_EINVAL on a NULL or non-256-byte-aligned pointer. */
+m1_status m1_bind_state(m1_ctx *ctx, const m1_fields *f);
+
+/* Opacity model (Sect. 2.1 source terms; chi = kappa_R + sigma):
+ * M1_OPAC_CONSTANT  params = {kappa_P, kappa_R, sigma}
+ * M1_OPAC_POWERLAW  params = {k0, rho0, alpha, T0, beta, sigma}:
+ *                   kappa_P = kappa_R = k0 (rho/rho0)^alpha (T/T0)^beta
+ * Re-evaluates the opacity cache when a state is bound. */
+m1_status m1_set_opacity_model(m1_ctx *ctx, int kind, const double *params);
+
+/* Bilinear table of log10 kappa (Planck and Rosseland) on nr x nt nodes that
+ * include both axis ends: node (i, j) at (lr_min + i h_r, lt_min + j h_t),
+ * host float32 arrays [nt][nr] (copied).  Looked up at
+ * (log10 rho + lr_off, log10 T + lt_off), clamped to the axes.  nr, nt >= 2. */
+m1_status m1_set_opacity_table(m1_ctx *ctx, int nr, int nt, double lr_min, double lr_max,
+                               double lt_min, double lt_max, double lr_off, double lt_off,
+                               const float *log10_kP, const float *log10_kR, double sigma);
+
+/* Use the MLP surrogate in place of the table (the table must be set: its
+ * axes and offsets define the network's input scaling). */
+m1_status m1_set_opacity_mlp(m1_ctx *ctx, const m1_mlp *w);
+
+/* Train the surrogate on the GPU (see m1_train_cfg); on success the trained
+ * network becomes the context's opacity source.  Synchronous. */
+m1_status m1_mlp_train(m1_ctx *ctx, const m1_train_cfg *cfg, m1_train_report *rep);
+
+/* Copy the current network parameters to host theta (M1_MLP_NPARAM floats)
+ * and norm[4].  Synchronous. */
+m1_status m1_mlp_get(m1_ctx *ctx, float *theta, double *norm);
+
+/* Loss and gradient of the surrogate (parameters theta, host float32
+ * [M1_MLP_NPARAM]) on n device samples (float32 [n][2] table coordinates, n
+ * a positive multiple of 64) against the bound table, computed by the
+ * training kernels: grad (host, M1_MLP_NPARAM floats), *loss.  theta
+ * becomes the context's network; the normalisation is the one set by
+ * m1_set_opacity_mlp or m1_mlp_train.  Synchronous. */
+m1_status m1_mlp_gradient(m1_ctx *ctx, const float *samples, long n, const float *theta, float *grad,
+                          double *loss);
+
+/* Evaluate the active opacity source on n device points: rho, T (double) ->
+ * kP, kR (double).  Asynchronous. */
+m1_status m1_opacity_eval(m1_ctx *ctx, long n, const double *rho, const double *T, double *kP,
+                          double *kR);
+
+/* Largest stable step for Courant number cfl: cfl / max_cells(c_hat
+ * sum_{d < ndim} 1/h_d) with h = (dr, r dtheta, r sin(theta) dphi) in
+ * spherical and (dR, R dphi, dz) in cylindrical grids (host computation). */
+m1_status m1_max_dt(const m1_ctx *ctx, double cfl, double *dt);
+
+/* Explicit transport step of length dt (> 0) from the bound (E, F) into the
+ * library's transported state (E*, F*).  Asynchronous.  M1_ESTATE if no
+ * state is bound. */
+m1_status m1_step_explicit(m1_ctx *ctx, double dt);
+
+/* Implicit source step of length dt from (E*, F*) and the gas: writes E, F,
+ * m, E_g of the bound arrays and refreshes the opacity cache at the new
+ * temperature.  Asynchronous.  M1_ESTATE unless the previous step call was
+ * m1_step_explicit. */
+m1_status m1_step_implicit(m1_ctx *ctx, double dt);
+
+/* Device pointers of the library's transported state E*, Fx*, Fy*, Fz*
+ * (valid after m1_step_explicit; owned by the library). */
+m1_status m1_transported(m1_ctx *ctx, void **E, void **Fx, void **Fy, void **Fz);
+
+/* Re-evaluate the opacity cache from the bound gas state (call after the
+ * caller changes rho, m or E_g outside the library). */
+m1_status m1_refresh_opacity(m1_ctx *ctx);
+
+/* Wait for the stream; reports a deferred device error as M1_EDEVICE. */
+m1_status m1_sync(m1_ctx *ctx);
+
+/* Synchronous reduction of the bound state (see m1_diag). */
+m1_status m1_diagnostics(m1_ctx *ctx, m1_diag *out);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *m1_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,352 @@
+// implicit.hip -- implicit radiation-matter step and the opacity cache.
+//
+// Per cell (Sect. 2.8): T^n from the gas energy, the 2x2 backward-Euler
+// system of Eq. implicit_matrix solved analytically in FP64, flux damping of
+// Eq. source_discrete2, the gas total energy and momentum from the rescaled
+// conservation laws (Sect. 2.7), f <= 1, and the opacity cache (rho kappa_P,
+// optical depth rho chi h_max) re-evaluated at the new temperature for the
+// next transport and implicit steps.
+#include "m1_internal.h"
+#include "m1_device.h"
+#include "opacity_device.h"
+#include "mlp_device.h"
+
+namespace m1 {
+
+template <typename R>
+struct IArgs {
+    R *E, *Fx, *Fy, *Fz;              // caller's radiation (written)
+    const R *Es, *Fxs, *Fys, *Fzs;    // transported state
+    const double *rho;
+    double *mx, *my, *mz, *Eg;
+    R *rkp, *tau;                     // opacity cache (read at T^n, written at T^{n+1})
+    int n[3];
+    int ndim;
+    Metric<R> m;
+    OpacityParams op;
+    ImplicitConsts k;
+    unsigned long long *cnt;
+};
+
+// largest cell extent over the active directions (optical depth of a cell)
+template <typename R>
+__device__ __forceinline__ R cell_hmax(const Metric<R> &m, int ndim, int i, int j, int k)
+{
+    R h = m.hd[0][i] * m.hI[0][i] * m.hJ[0][j];
+    if (ndim >= 2) {
+        const R h1 = m.hd[1][j] * m.hI[1][i] * m.hJ[1][j];
+        h = h1 > h ? h1 : h;
+    }
+    if (ndim >= 3) {
+        const R h2 = m.hd[2][k] * m.hI[2][i] * m.hJ[2][j];
+        h = h2 > h ? h2 : h;
+    }
+    return h;
+}
+
+__device__ __forceinline__ double gas_T(double rho, double mx, double my, double mz, double Eg,
+                                        double gamma)
+{
+    const double Cv = rho / (gamma - 1.0);
+    return (Eg - 0.5 * (mx * mx + my * my + mz * mz) / rho) / Cv;
+}
+
+// One cell of the implicit step; returns the new gas temperature.
+template <typename R, bool CONST_OPAC>
+__device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i, int j, int k)
+{
+    const double rho = a.rho[id];
+    double mx = a.mx[id], my = a.my[id], mz = a.mz[id], Eg = a.Eg[id];
+    const double gam = a.k.gamma;
+    const double Cv = rho / (gam - 1.0);
+    const double T = gas_T(rho, mx, my, mz, Eg, gam);
+    double rkP, rchi;
+    if (CONST_OPAC) {
+        rkP = rho * a.op.kP;
+        rchi = rho * (a.op.kR + a.op.sigma);
+    } else {
+        rkP = double(a.rkp[id]);
+        rchi = double(a.tau[id]) / double(cell_hmax(a.m, a.ndim, i, j, k));
+    }
+    const double Es = double(a.Es[id]);
+    const double Fs[3] = {double(a.Fxs[id]), double(a.Fys[id]), double(a.Fzs[id])};
+    // Eq. implicit_matrix with gamma_abs,red = dt c_hat kappa_P rho and
+    // gamma_abs = dt c kappa_P rho, inverted by Cramer's rule in a
+    // cancellation-free arrangement (det > 0)
+    const double gr = a.k.dt * a.k.c_hat * rkP;
+    const double g = a.k.dt * a.k.c * rkP;
+    const double aT3 = a.k.a * T * T * T, aT4 = aT3 * T;
+    const double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
+    double E1 = (Cv * (Es + gr * aT4) + 4.0 * g * aT3 * Es) / det;
+    const double damp = 1.0 + a.k.dt * a.k.c_hat * rchi;   // Eq. source_discrete2
+    double F1[3] = {Fs[0] / damp, Fs[1] / damp, Fs[2] / damp};
+    const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
+    if (Fn > E1) {
+        const double s = E1 / Fn;
+        F1[0] *= s;
+        F1[1] *= s;
+        F1[2] *= s;
+        atomicAdd(&a.cnt[2], 1ull);
+    }
+    // stored (possibly float) values define the exchanged amounts, so the
+    // rescaled totals E_g + (c/c_hat) E and m + F/c_hat are conserved
+    const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
+    const double inv_ch = 1.0 / a.k.c_hat;
+    Eg -= (a.k.c * inv_ch) * (double(E1r) - Es);
+    mx -= (double(F1r[0]) - Fs[0]) * inv_ch;
+    my -= (double(F1r[1]) - Fs[1]) * inv_ch;
+    mz -= (double(F1r[2]) - Fs[2]) * inv_ch;
+    a.E[id] = E1r;
+    a.Fx[id] = F1r[0];
+    a.Fy[id] = F1r[1];
+    a.Fz[id] = F1r[2];
+    a.Eg[id] = Eg;
+    a.mx[id] = mx;
+    a.my[id] = my;
+    a.mz[id] = mz;
+    return gas_T(rho, mx, my, mz, Eg, gam);
+}
+
+template <typename R, int OPK>
+__global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
+{
+    const int n0 = a.n[0], n1 = a.n[1];
+    const int N = n0 * n1 * a.n[2];
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    const double T1 = implicit_cell<R, OPK == OPK_CONST>(a, id, i, j, k);
+    if (OPK != OPK_CONST) {
+        const R rho = R(a.rho[id]);
+        R kP, kR;
+        opacity_analytic<R, OPK>(a.op, rho, R(T1), kP, kR);
+        a.rkp[id] = rho * kP;
+        a.tau[id] = rho * (kR + R(a.op.sigma)) * cell_hmax(a.m, a.ndim, i, j, k);
+    }
+}
+
+// MLP opacity: every lane of a wavefront takes part in the network
+// evaluation, so the grid strides over 64-cell chunks without early exits.
+template <typename R>
+__global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
+{
+    const int n0 = a.n[0], n1 = a.n[1];
+    const int N = n0 * n1 * a.n[2];
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwave = (gridDim.x * blockDim.x) >> 6;
+    MlpWave net;
+    net.load(a.op.mlp, lane);
+    for (int base = wave * 64; base < N; base += nwave * 64) {
+        const int id = base + lane;
+        const bool live = id < N;
+        const int idc = live ? id : N - 1;
+        const int i = idc % n0, j = (idc / n0) % n1, k = idc / (n0 * n1);
+        double T1 = 1.0;
+        if (live) T1 = implicit_cell<R, false>(a, id, i, j, k);
+        const float rho = float(a.rho[idc]);
+        float kP, kR;
+        net.opacity(a.op, rho, float(T1), lane, kP, kR);
+        if (live) {
+            a.rkp[id] = R(rho * kP);
+            a.tau[id] = R(rho * (kR + float(a.op.sigma))) * cell_hmax(a.m, a.ndim, i, j, k);
+        }
+    }
+}
+
+template <typename R>
+static void fill_args(m1_ctx *c, IArgs<R> &a, const Metric<R> &met, double dt)
+{
+    a.E = static_cast<R *>(c->f.E);
+    a.Fx = static_cast<R *>(c->f.Fx);
+    a.Fy = static_cast<R *>(c->f.Fy);
+    a.Fz = static_cast<R *>(c->f.Fz);
+    a.Es = static_cast<const R *>(c->star[0]);
+    a.Fxs = static_cast<const R *>(c->star[1]);
+    a.Fys = static_cast<const R *>(c->star[2]);
+    a.Fzs = static_cast<const R *>(c->star[3]);
+    a.rho = c->f.rho;
+    a.mx = c->f.mx;
+    a.my = c->f.my;
+    a.mz = c->f.mz;
+    a.Eg = c->f.Eg;
+    a.rkp = static_cast<R *>(c->rkp);
+    a.tau = static_cast<R *>(c->tau);
+    for (int d = 0; d < 3; ++d) a.n[d] = c->n[d];
+    a.ndim = c->ndim;
+    a.m = met;
+    a.op = c->op;
+    a.k.dt = dt;
+    a.k.c_hat = c->c_hat;
+    a.k.c = c->par.c;
+    a.k.a = c->par.a_rad;
+    a.k.gamma = c->par.gamma;
+    a.cnt = c->cnt;
+}
+
+static int mlp_grid(int N)
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    const int chunks = (N + 63) / 64;
+    int blocks = cus * 8;                       // 4 waves per block, 32 waves per CU
+    const int need = (chunks + 3) / 4;
+    return need < blocks ? (need > 0 ? need : 1) : blocks;
+}
+
+template <typename R>
+static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met)
+{
+    IArgs<R> a;
+    fill_args(c, a, met, dt);
+    const int N = c->n[0] * c->n[1] * c->n[2];
+    dim3 block(256), grid((N + 255) / 256);
+    switch (c->op.kind) {
+    case OPK_CONST: hipLaunchKernelGGL((k_implicit<R, OPK_CONST>), grid, block, 0, c->stream, a); break;
+    case OPK_POWERLAW: hipLaunchKernelGGL((k_implicit<R, OPK_POWERLAW>), grid, block, 0, c->stream, a); break;
+    case OPK_TABLE: hipLaunchKernelGGL((k_implicit<R, OPK_TABLE>), grid, block, 0, c->stream, a); break;
+    default:
+        hipLaunchKernelGGL((k_implicit_mlp<R>), dim3(mlp_grid(N)), block, 0, c->stream, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_implicit(m1_ctx *c, double dt)
+{
+    if (c->par.precision == M1_F32) return launch_i<float>(c, dt, c->met32);
+    return launch_i<double>(c, dt, c->met64);
+}
+
+// ---------------------------------------------------------------------------
+// opacity cache from the current gas state
+// ---------------------------------------------------------------------------
+
+template <typename R, int OPK>
+__global__ void __launch_bounds__(256) k_opacity_init(IArgs<R> a)
+{
+    const int n0 = a.n[0], n1 = a.n[1];
+    const int N = n0 * n1 * a.n[2];
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    const double T = gas_T(a.rho[id], a.mx[id], a.my[id], a.mz[id], a.Eg[id], a.k.gamma);
+    const R rho = R(a.rho[id]);
+    R kP, kR;
+    opacity_analytic<R, OPK>(a.op, rho, R(T), kP, kR);
+    a.rkp[id] = rho * kP;
+    a.tau[id] = rho * (kR + R(a.op.sigma)) * cell_hmax(a.m, a.ndim, i, j, k);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_opacity_init_mlp(IArgs<R> a)
+{
+    const int n0 = a.n[0], n1 = a.n[1];
+    const int N = n0 * n1 * a.n[2];
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwave = (gridDim.x * blockDim.x) >> 6;
+    MlpWave net;
+    net.load(a.op.mlp, lane);
+    for (int base = wave * 64; base < N; base += nwave * 64) {
+        const int id = base + lane;
+        const bool live = id < N;
+        const int idc = live ? id : N - 1;
+        const int i = idc % n0, j = (idc / n0) % n1, k = idc / (n0 * n1);
+        const double T = gas_T(a.rho[idc], a.mx[idc], a.my[idc], a.mz[idc], a.Eg[idc], a.k.gamma);
+        const float rho = float(a.rho[idc]);
+        float kP, kR;
+        net.opacity(a.op, rho, float(T), lane, kP, kR);
+        if (live) {
+            a.rkp[id] = R(rho * kP);
+            a.tau[id] = R(rho * (kR + float(a.op.sigma))) * cell_hmax(a.m, a.ndim, i, j, k);
+        }
+    }
+}
+
+template <typename R>
+static hipError_t launch_init(m1_ctx *c, const Metric<R> &met)
+{
+    IArgs<R> a;
+    fill_args(c, a, met, 0.0);
+    const int N = c->n[0] * c->n[1] * c->n[2];
+    dim3 block(256), grid((N + 255) / 256);
+    switch (c->op.kind) {
+    case OPK_CONST: hipLaunchKernelGGL((k_opacity_init<R, OPK_CONST>), grid, block, 0, c->stream, a); break;
+    case OPK_POWERLAW: hipLaunchKernelGGL((k_opacity_init<R, OPK_POWERLAW>), grid, block, 0, c->stream, a); break;
+    case OPK_TABLE: hipLaunchKernelGGL((k_opacity_init<R, OPK_TABLE>), grid, block, 0, c->stream, a); break;
+    default:
+        hipLaunchKernelGGL((k_opacity_init_mlp<R>), dim3(mlp_grid(N)), block, 0, c->stream, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_opacity_init(m1_ctx *c)
+{
+    if (c->par.precision == M1_F32) return launch_init<float>(c, c->met32);
+    return launch_init<double>(c, c->met64);
+}
+
+// ---------------------------------------------------------------------------
+// pointwise evaluation of the active opacity source (tests, tools)
+// ---------------------------------------------------------------------------
+
+template <int OPK>
+__global__ void __launch_bounds__(256) k_opacity_eval(OpacityParams op, long n, const double *rho,
+                                                      const double *T, double *kP, double *kR)
+{
+    const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    double a, b;
+    opacity_analytic<double, OPK>(op, rho[id], T[id], a, b);
+    kP[id] = a;
+    kR[id] = b;
+}
+
+__global__ void __launch_bounds__(256) k_opacity_eval_mlp(OpacityParams op, long n, const double *rho,
+                                                          const double *T, double *kP, double *kR)
+{
+    const int lane = threadIdx.x & 63;
+    const long wave = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
+    const long nwave = (gridDim.x * (long)blockDim.x) >> 6;
+    MlpWave net;
+    net.load(op.mlp, lane);
+    for (long base = wave * 64; base < n; base += nwave * 64) {
+        const long id = base + lane;
+        const bool live = id < n;
+        const long idc = live ? id : n - 1;
+        float a, b;
+        net.opacity(op, float(rho[idc]), float(T[idc]), lane, a, b);
+        if (live) {
+            kP[id] = a;
+            kR[id] = b;
+        }
+    }
+}
+
+hipError_t launch_opacity_eval(m1_ctx *c, long n, const double *rho, const double *T, double *kP,
+                               double *kR)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 block(256);
+    dim3 grid((unsigned)((n + 255) / 256));
+    switch (c->op.kind) {
+    case OPK_CONST: hipLaunchKernelGGL((k_opacity_eval<OPK_CONST>), grid, block, 0, c->stream, c->op, n, rho, T, kP, kR); break;
+    case OPK_POWERLAW: hipLaunchKernelGGL((k_opacity_eval<OPK_POWERLAW>), grid, block, 0, c->stream, c->op, n, rho, T, kP, kR); break;
+    case OPK_TABLE: hipLaunchKernelGGL((k_opacity_eval<OPK_TABLE>), grid, block, 0, c->stream, c->op, n, rho, T, kP, kR); break;
+    default: {
+        const long chunks = (n + 63) / 64;
+        long blocks = (chunks + 3) / 4;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_opacity_eval_mlp, dim3((unsigned)blocks), block, 0, c->stream, c->op, n, rho, T, kP, kR);
+        break;
+    }
+    }
+    return hipGetLastError();
+}
+
+} // namespace m1

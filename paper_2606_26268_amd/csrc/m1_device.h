@@ -1,0 +1,118 @@
+// m1_device.h -- device-side building blocks of the M1 step for gfx950:
+// Levermore closure with the Sect. 2.6 signal speeds and the physical flux
+// of one state, the HLL interface flux with the optical-depth limiter, the
+// van Leer slope and the f-preserving face fix (Eq. f_reconstruct).
+// Templated on the working precision R (double or float).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace m1 {
+
+template <typename R> struct Num;
+template <> struct Num<double> {
+    static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+};
+template <> struct Num<float> {
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+};
+
+// Closure quantities of one radiation state (E, F) seen from direction d:
+// lambda_-, lambda_+ (Sect. 2.6) and the flux (F_d, E D_{xd}, E D_{yd},
+// E D_{zd}) (Sect. 2.1, Eqs. rad1/rad2), all in units of c_hat.
+template <typename R>
+struct Wave {
+    R lm, lp;
+    R phi[4];
+};
+
+template <typename R, int D>
+__device__ __forceinline__ Wave<R> closure_wave(R E, R Fx, R Fy, R Fz)
+{
+    Wave<R> w;
+    const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const R Fn = Num<R>::sqrt_(F2);
+    R f = Fn / E;
+    f = f > R(1) ? R(1) : f;
+    const R f2 = f * f;
+    const R s = Num<R>::sqrt_(R(4) - R(3) * f2);
+    const R xi = (R(3) + R(4) * f2) / (R(5) + R(2) * s);
+    const R Fd = D == 0 ? Fx : (D == 1 ? Fy : Fz);
+    // n = F / |F| (n = 0 for F = 0)
+    const R inv = Fn > R(0) ? R(1) / Fn : R(0);
+    const R mu = Fd * inv;
+    R z2 = (R(2) / R(3)) * (R(4) - R(3) * f2 - s) + R(2) * mu * mu * (R(2) - f2 - s);
+    z2 = z2 < R(0) ? R(0) : z2;
+    const R zeta = Num<R>::sqrt_(z2);
+    const R a = (f * mu - zeta) / s, b = (f * mu + zeta) / s;
+    w.lm = a < b ? a : b;
+    w.lp = a < b ? b : a;
+    const R iso = R(0.5) * (R(1) - xi) * E;
+    const R an = R(0.5) * (R(3) * xi - R(1)) * E;
+    const R nd = mu;
+    w.phi[0] = Fd;
+    w.phi[1] = an * (Fx * inv) * nd + (D == 0 ? iso : R(0));
+    w.phi[2] = an * (Fy * inv) * nd + (D == 1 ? iso : R(0));
+    w.phi[3] = an * (Fz * inv) * nd + (D == 2 ? iso : R(0));
+    return w;
+}
+
+// HLL flux c_hat * Phi* between face states UL | UR (Sect. 2.5) with the
+// speeds lambda_L = min lambda_-, lambda_R = max lambda_+ clamped to
+// -+4/(3 tau) for tau > 0 (Sect. 2.6), S_L = min(lambda_L, 0),
+// S_R = max(lambda_R, 0); S_L = S_R = 0 falls back to the average flux.
+template <typename R, int D>
+__device__ __forceinline__ void hll_flux(const R UL[4], const R UR[4], R tau, R c_hat, R out[4])
+{
+    const Wave<R> wl = closure_wave<R, D>(UL[0], UL[1], UL[2], UL[3]);
+    const Wave<R> wr = closure_wave<R, D>(UR[0], UR[1], UR[2], UR[3]);
+    R lamL = wl.lm < wr.lm ? wl.lm : wr.lm;
+    R lamR = wl.lp > wr.lp ? wl.lp : wr.lp;
+    if (tau > R(0)) {
+        const R lim = R(4) / (R(3) * tau);
+        lamL = lamL < -lim ? -lim : lamL;
+        lamR = lamR > lim ? lim : lamR;
+    }
+    const R SL = lamL < R(0) ? lamL : R(0);
+    const R SR = lamR > R(0) ? lamR : R(0);
+    if (SR > SL) {
+        const R k = c_hat / (SR - SL);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            out[q] = k * (SR * wl.phi[q] - SL * wr.phi[q] + SL * SR * (UR[q] - UL[q]));
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = c_hat * R(0.5) * (wl.phi[q] + wr.phi[q]);
+    }
+}
+
+// van Leer limited slope of divided differences (harmonic mean, 0 at extrema).
+template <typename R>
+__device__ __forceinline__ R vanleer(R dl, R dr)
+{
+    const R p = dl * dr;
+    return p > R(0) ? (R(2) * p) / (dl + dr) : R(0);
+}
+
+// f-preserving fix of a reconstructed face state against its donor cell
+// centre (Eq. f_reconstruct): keep F_face iff f_face <= 1 and f_face >
+// f_centre, else F_face = F_centre * E_face / E_centre; E_face <= 0 falls back
+// to the centre state.
+template <typename R>
+__device__ __forceinline__ void ffix(R U[4], const R C[4])
+{
+    if (U[0] > R(0)) {
+        const R ff = Num<R>::sqrt_(U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0];
+        const R fc = Num<R>::sqrt_(C[1] * C[1] + C[2] * C[2] + C[3] * C[3]) / C[0];
+        if (!(ff <= R(1) && ff > fc)) {
+            const R r = U[0] / C[0];
+            U[1] = C[1] * r;
+            U[2] = C[2] * r;
+            U[3] = C[3] * r;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) U[q] = C[q];
+    }
+}
+
+} // namespace m1

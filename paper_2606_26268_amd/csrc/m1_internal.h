@@ -1,0 +1,97 @@
+// m1_internal.h -- library-internal context, metric layout and kernel
+// launchers shared by the host API and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/m1.h"
+
+namespace m1 {
+
+// Separable metric of the grid, one set of 1D arrays per direction, in the
+// working precision R.  Reconstruction arrays are padded with two ghost
+// entries on each side (index t + 2 for t in [-2, n+1]).
+template <typename R>
+struct Metric {
+    const R *winv[3];  // 1 / (x_t - x_{t-1}) between centres, t in [-1, n+1]
+    const R *hp[3];    // x_{t+1/2} - x_t
+    const R *hm[3];    // x_t - x_{t-1/2}
+    // face area over cell volume for direction d:
+    //   A_lo/V = alo[d][t] * trA[d][i] * trB[d][j], A_hi/V likewise with ahi
+    const R *alo[3], *ahi[3], *trA[3], *trB[3];
+    // extent of cell (i,j,k) along d: hd[d][t] * hI[d][i] * hJ[d][j]
+    const R *hd[3], *hI[3], *hJ[3];
+    const R *inv_reff;  // 1 / r_eff (per i), 0 for Cartesian
+    const R *cot_eff;   // cot(theta)_eff (per j), spherical only
+};
+
+enum OpacKind { OPK_CONST = 0, OPK_POWERLAW = 1, OPK_TABLE = 2, OPK_MLP = 3 };
+
+struct OpacityParams {
+    int kind;
+    double kP, kR, sigma;                       // constant
+    double k0, rho0, alpha, T0, beta;           // power law
+    int nr, nt;                                 // table
+    double lr0, lr1, lt0, lt1, lr_off, lt_off;
+    const float *tab_kP, *tab_kR;               // device
+    const float *mlp;                           // device, packed (see mlp.hip)
+    double norm[4];
+};
+
+struct ImplicitConsts {
+    double dt, c_hat, c, a, gamma;
+};
+
+} // namespace m1
+
+struct m1_ctx {
+    int ndim = 1;
+    int n[3] = {1, 1, 1};
+    int bc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    int geom = 0;
+    double c_hat = 1.0;
+    m1_params par{};
+    std::vector<double> faces[3];
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // metric arrays (one allocation) in both precisions
+    void *metric_buf = nullptr;
+    m1::Metric<double> met64{};
+    m1::Metric<float> met32{};
+    double *vol_dev[3] = {nullptr, nullptr, nullptr};  // volume factors (double)
+    int ign[3] = {0, 0, 0};   // inactive direction with unequal face areas
+
+    // bound state
+    bool bound = false;
+    m1_fields f{};
+    void *scratch = nullptr;  // E*, Fx*, Fy*, Fz*, tau, rkp (form precision)
+    void *star[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *tau = nullptr, *rkp = nullptr;
+    unsigned long long *cnt = nullptr;     // 4 fix-up counters
+    double *partials = nullptr;            // reduction scratch
+    int npartial = 0;
+    bool transported = false;
+
+    // opacity
+    m1::OpacityParams op{};
+    float *table_dev = nullptr;            // [2][nt][nr]
+    float *mlp_dev = nullptr;              // packed network
+    std::vector<float> mlp_theta;          // host copy of the float32 master
+};
+
+namespace m1 {
+// kernel launchers (defined in the .hip translation units)
+hipError_t launch_transport(m1_ctx *c, double dt);
+hipError_t launch_implicit(m1_ctx *c, double dt);
+hipError_t launch_opacity_init(m1_ctx *c);
+hipError_t launch_opacity_eval(m1_ctx *c, long n, const double *rho, const double *T, double *kP,
+                               double *kR);
+hipError_t launch_diag(m1_ctx *c, double out[8]);
+int mlp_pack(m1_ctx *c, const float *theta, const double *norm);
+int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep);
+int mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, float *grad, double *loss);
+void set_error(const std::string &msg);
+} // namespace m1

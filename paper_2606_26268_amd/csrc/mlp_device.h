@@ -1,0 +1,177 @@
+// mlp_device.h -- wavefront-cooperative evaluation of the opacity surrogate
+//   x (2) -> h1 = tanh(W1 x + b1) (64) -> h2 = tanh(W2 h1 + b2) (64)
+//         -> y = W3 h2 + b3 + Ws x (2),  log10 kappa = y * std + mean
+// for 64 inputs at once (one per lane).  Layers 1 and 3 run on the vector
+// ALU in FP32; the 64x64 layer runs on the bfloat16 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with each operand split into
+// a bfloat16 high part and a bfloat16 remainder, keeping hi*hi + hi*lo +
+// lo*hi (about 16 significant bits per product).
+//
+// Matrix-core operand layout used (32x32x16): lane l, g = l / 32, holds
+//   A[m = l % 32][k = 8 g + e], B[k = 8 g + e][n = l % 32], e = 0..7,
+//   D[row = 8 (i / 4) + 4 g + (i % 4)][col = l % 32], i = 0..15.
+// The product is computed as Z2^T = W2 * H1^T: A = W2 (rows: output units),
+// B = H1^T (columns: samples).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "m1_internal.h"
+#include "opacity_device.h"
+
+namespace m1 {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Packed network (float words):
+//   [0, 128)      W1[64][2]
+//   [128, 192)    b1[64]
+//   [192, 256)    b2[64]
+//   [256, 384)    W3[2][64]
+//   [384, 386)    b3[2]
+//   [386, 390)    Ws[2][2]
+//   [390, 394)    norm: mean_P, std_P, mean_R, std_R
+//   [512, 2560)   W2 hi fragments: bf16 [mt 2][ks 4][lane 64][8]
+//   [2560, 4608)  W2 lo fragments, same order
+constexpr int MLP_PACK_FLOATS = 4608;
+constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 128, MLP_OFF_B2 = 192, MLP_OFF_W3 = 256;
+constexpr int MLP_OFF_B3 = 384, MLP_OFF_WS = 386, MLP_OFF_NORM = 390;
+constexpr int MLP_OFF_W2HI = 512, MLP_OFF_W2LO = 2560;
+
+__device__ __forceinline__ float fast_tanh(float x)
+{
+    // tanh x = sign(x) (1 - e) / (1 + e), e = exp(-2 |x|), exp via exp2
+    const float ax = __builtin_fabsf(x);
+    const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * ax);
+    const float t = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+    return __builtin_copysignf(t, x);
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
+
+struct MlpWave {
+    const float *p;
+    bf16x8 w2h[2][4], w2l[2][4];
+
+    __device__ __forceinline__ void load(const float *packed, int lane)
+    {
+        p = packed;
+        const bf16x8 *hi = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_W2HI);
+        const bf16x8 *lo = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_W2LO);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                w2h[mt][ks] = hi[(mt * 4 + ks) * 64 + lane];
+                w2l[mt][ks] = lo[(mt * 4 + ks) * 64 + lane];
+            }
+    }
+
+    // Layer 1 for the lane's own input: h1[0..63].
+    __device__ __forceinline__ void layer1(float x0, float x1, float h1[64]) const
+    {
+#pragma unroll
+        for (int u = 0; u < 64; ++u)
+            h1[u] = fast_tanh(p[MLP_OFF_W1 + 2 * u] * x0 + p[MLP_OFF_W1 + 2 * u + 1] * x1 +
+                              p[MLP_OFF_B1 + u]);
+    }
+
+    // Layer 2 pre-activations Z2^T tiles acc[mt][nt]: lane holds samples
+    // 32 nt + l % 32, output units 32 mt + 8 (i / 4) + 4 g + (i % 4).
+    __device__ __forceinline__ void layer2(const float h1[64], int lane, f32x16 acc[2][2]) const
+    {
+        const int g = lane >> 5;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[mt][nt][i] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            // own values of chunk g and the partner's (lane ^ 32) of chunk g
+            bf16x8 own_h, own_l, oth_h, oth_l;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float mine = g ? h1[16 * ks + 8 + e] : h1[16 * ks + e];
+                const float send = g ? h1[16 * ks + e] : h1[16 * ks + 8 + e];
+                const float recv = __shfl_xor(send, 32);
+                const __bf16 mh = to_bf16(mine), rh = to_bf16(recv);
+                own_h[e] = mh;
+                own_l[e] = to_bf16(mine - float(mh));
+                oth_h[e] = rh;
+                oth_l[e] = to_bf16(recv - float(rh));
+            }
+            // tile nt: lanes of group nt supply their own sample
+            const bf16x8 b0h = g == 0 ? own_h : oth_h, b0l = g == 0 ? own_l : oth_l;
+            const bf16x8 b1h = g == 1 ? own_h : oth_h, b1l = g == 1 ? own_l : oth_l;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2h[mt][ks], b0h, acc[mt][0], 0, 0, 0);
+                acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2h[mt][ks], b0l, acc[mt][0], 0, 0, 0);
+                acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2l[mt][ks], b0h, acc[mt][0], 0, 0, 0);
+                acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2h[mt][ks], b1h, acc[mt][1], 0, 0, 0);
+                acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2h[mt][ks], b1l, acc[mt][1], 0, 0, 0);
+                acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2l[mt][ks], b1h, acc[mt][1], 0, 0, 0);
+            }
+        }
+    }
+
+    // Output unit held in slot i of tile mt by lane group g.
+    static __device__ __forceinline__ int unit(int mt, int i, int g)
+    {
+        return 32 * mt + 8 * (i >> 2) + 4 * g + (i & 3);
+    }
+
+    // Full forward for the lane's own input x -> y (normalised outputs).
+    __device__ __forceinline__ void forward(float x0, float x1, int lane, float &y0, float &y1) const
+    {
+        float h1[64];
+        layer1(x0, x1, h1);
+        f32x16 acc[2][2];
+        layer2(h1, lane, acc);
+        const int g = lane >> 5;
+        float part[2][2] = {{0.f, 0.f}, {0.f, 0.f}};  // [nt][output]
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int u = unit(mt, i, g);
+                    const float h2 = fast_tanh(acc[mt][nt][i] + p[MLP_OFF_B2 + u]);
+                    part[nt][0] += p[MLP_OFF_W3 + u] * h2;
+                    part[nt][1] += p[MLP_OFF_W3 + 64 + u] * h2;
+                }
+        // the partner lane holds the other 32 units of the same samples
+        const float s0 = g ? part[0][0] : part[1][0];
+        const float s1 = g ? part[0][1] : part[1][1];
+        const float r0 = __shfl_xor(s0, 32), r1 = __shfl_xor(s1, 32);
+        const float m0 = g ? part[1][0] : part[0][0];
+        const float m1 = g ? part[1][1] : part[0][1];
+        y0 = m0 + r0 + p[MLP_OFF_B3] + p[MLP_OFF_WS] * x0 + p[MLP_OFF_WS + 1] * x1;
+        y1 = m1 + r1 + p[MLP_OFF_B3 + 1] + p[MLP_OFF_WS + 2] * x0 + p[MLP_OFF_WS + 3] * x1;
+    }
+
+    // Network inputs from (rho, T) through the table axes and offsets.
+    static __device__ __forceinline__ void inputs(const OpacityParams &op, float rho, float T, float &x0,
+                                                  float &x1)
+    {
+        float lr, lt;
+        table_coords<float>(op, rho, T, lr, lt);
+        x0 = 2.0f * (lr - float(op.lr0)) / float(op.lr1 - op.lr0) - 1.0f;
+        x1 = 2.0f * (lt - float(op.lt0)) / float(op.lt1 - op.lt0) - 1.0f;
+    }
+
+    __device__ __forceinline__ void opacity(const OpacityParams &op, float rho, float T, int lane, float &kP,
+                                            float &kR) const
+    {
+        float x0, x1, y0, y1;
+        inputs(op, rho, T, x0, x1);
+        forward(x0, x1, lane, y0, y1);
+        kP = exp10f(y0 * p[MLP_OFF_NORM + 1] + p[MLP_OFF_NORM + 0]);
+        kR = exp10f(y1 * p[MLP_OFF_NORM + 3] + p[MLP_OFF_NORM + 2]);
+    }
+};
+
+} // namespace m1

@@ -1,0 +1,35 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/m1.h declares; the Python binding names the same set."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "m1.h")
+LIB = os.path.join(ROOT, "paper_2606_26268_amd", "libm1.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(m1_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("m1_create", "m1_set_opacity_table", "m1_step_explicit", "m1_step_implicit"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2606_26268_amd import m1
+    assert sorted(m1.EXPORTS) == declared()

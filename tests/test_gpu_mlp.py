@@ -1,0 +1,137 @@
+"""The learned opacity surrogate on the GPU: inference and back-propagation
+against the oracle (bfloat16 split emulation), training to the 1e-3
+relative-error target judged by the oracle's bilinear table, and a full
+spherical run with the network in place of the table."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_26268_amd import inputs as I
+from tests.gpu_common import TOL_F32, assert_close, rel_errors, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def table_norm(tab):
+    """mean / std of each table (the network's output scaling, an input)."""
+    a = tab["log10_kP"].astype(np.float64)
+    b = tab["log10_kR"].astype(np.float64)
+    return np.array([a.mean(), a.std(), b.mean(), b.std()])
+
+
+def _theta(seed=7):
+    th = I.mlp_init(seed)
+    rng = np.random.default_rng(seed)
+    return (th + 0.05 * rng.normal(size=th.size)).astype(np.float32)
+
+
+def _ctx_with_table(prob_like=None):
+    from paper_2606_26268_amd import m1
+    tab = I.make_table()
+    p = I.make_uniform(I.CARTESIAN, (64, 1, 1), 1)
+    p.opacity = tab
+    s = m1.Solver(p, "p64")
+    return m1, s, tab
+
+
+def test_inference_matches_oracle(orc):
+    m1, s, tab = _ctx_with_table()
+    th, norm = _theta(), table_norm(tab)
+    m1.m1_set_opacity_mlp(s.ctx, th, norm)
+    rng = np.random.default_rng(0)
+    n = 4099                                   # ragged against 64-lane waves
+    rho = 10 ** rng.uniform(-7.5, 5.5, n)      # covers clamping at both ends
+    T = 10 ** rng.uniform(-2.5, 2.5, n)
+    dev = lambda a: torch.from_numpy(a).to("cuda")
+    kP, kR = torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda")
+    m1.m1_opacity_eval(s.ctx, n, dev(rho), dev(T), kP, kR)
+    s.sync()
+    p = I.make_uniform(I.CARTESIAN, (2, 1, 1), 1)
+    p.opacity = dict(tab, kind=I.OPAC_MLP)
+    o = orc.Oracle(p, dict(theta=th.astype(np.float64), norm=norm, bf16=True))
+    rP, rR = o.opacity(rho, T)
+    dP = np.abs(np.log10(kP.cpu().numpy()) - np.log10(rP))
+    dR = np.abs(np.log10(kR.cpu().numpy()) - np.log10(rR))
+    say(f"  mlp inference max |dlog10 k|: P {dP.max():.2e} R {dR.max():.2e}")
+    assert dP.max() < 2e-5 and dR.max() < 2e-5
+    s.close()
+
+
+def test_gradient_matches_oracle(orc):
+    m1, s, tab = _ctx_with_table()
+    th, norm = _theta(11), table_norm(tab)
+    m1.m1_set_opacity_mlp(s.ctx, th, norm)
+    n = 256
+    smp = I.mlp_samples(n, 123)
+    loss, g = m1.m1_mlp_gradient(s.ctx, torch.from_numpy(smp).to("cuda"), n, th)
+    # oracle: inputs scaled to [-1, 1], targets from the oracle's table lookup
+    p = I.make_uniform(I.CARTESIAN, (2, 1, 1), 1)
+    p.opacity = tab
+    o = orc.Oracle(p)
+    lr, lt = smp[:, 0].astype(np.float64), smp[:, 1].astype(np.float64)
+    kP, kR = o.opacity(10 ** (lr - tab["lr_off"]), 10 ** (lt - tab["lt_off"]))
+    t = np.stack([(np.log10(kP) - norm[0]) / norm[1], (np.log10(kR) - norm[2]) / norm[3]], axis=1)
+    x = np.stack([2 * (lr - tab["lr0"]) / (tab["lr1"] - tab["lr0"]) - 1,
+                  2 * (lt - tab["lt0"]) / (tab["lt1"] - tab["lt0"]) - 1], axis=1)
+    rloss, rg = orc.mlp_loss_grad(th.astype(np.float64), x, t, bf16=True)
+    assert abs(loss - rloss) <= 1e-4 * rloss
+    off = 0
+    for name, shp in I.MLP_LAYOUT:
+        k = int(np.prod(shp))
+        a, b = g[off:off + k].astype(np.float64), rg[off:off + k]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        say(f"  grad {name}: rel-L2 {err:.2e}")
+        assert err <= 1e-4, name
+        off += k
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """Train on 1e6 table samples (seed 4), hold out 1e5 (seed 5)."""
+    m1, s, tab = _ctx_with_table()
+    ntr, nev = 1_000_000, 100_000
+    smp = np.concatenate([I.mlp_samples(ntr, 4), I.mlp_samples(nev, 5)])
+    dsmp = torch.from_numpy(smp).to("cuda")
+    rep = m1.m1_mlp_train(s.ctx, dsmp, ntr, nev, I.mlp_init(7), batch=1024, steps=30000,
+                          lr=2e-3, lr_final=2e-6)
+    say(f"  training: {rep}")
+    th, norm = m1.m1_mlp_get(s.ctx)
+    return m1, s, tab, smp[ntr:], th, norm, rep
+
+
+def test_training_reaches_target(orc, trained):
+    m1, s, tab, held, th, norm, rep = trained
+    assert rep["max_rel_err_P"] <= 1e-3 and rep["max_rel_err_R"] <= 1e-3, rep
+    # judge independently with the oracle's bilinear lookup on the held-out set
+    n = held.shape[0]
+    lr, lt = held[:, 0].astype(np.float64), held[:, 1].astype(np.float64)
+    rho = torch.from_numpy(10 ** (lr - tab["lr_off"])).to("cuda")
+    T = torch.from_numpy(10 ** (lt - tab["lt_off"])).to("cuda")
+    kP, kR = torch.empty_like(rho), torch.empty_like(rho)
+    m1.m1_opacity_eval(s.ctx, n, rho, T, kP, kR)
+    s.sync()
+    p = I.make_uniform(I.CARTESIAN, (2, 1, 1), 1)
+    p.opacity = tab
+    rP, rR = orc.Oracle(p).opacity(rho.cpu().numpy(), T.cpu().numpy())
+    eP = np.abs(kP.cpu().numpy() / rP - 1).max()
+    eR = np.abs(kR.cpu().numpy() / rR - 1).max()
+    say(f"  held-out max rel err vs oracle table: P {eP:.2e} R {eR:.2e}")
+    assert eP <= 1e-3 and eR <= 1e-3
+
+
+def test_c4_spherical_run_with_network(orc, trained):
+    """Reduced spherical grid, 50 steps with the trained network vs the
+    oracle running the same network (bfloat16 split emulation)."""
+    m1, s, tab, held, th, norm, rep = trained
+    p = I.make_c4(nr=48, nth=24, nph=48, dt=4.0e-5)
+    mlp = dict(theta=th, norm=norm)
+    ref, _ = run_oracle(orc, p, 50, mlp=dict(theta=th.astype(np.float64), norm=norm, bf16=True))
+    got, _ = run_gpu(p, "f32", 50, mlp=mlp)
+    assert_close(got, ref, dict(l1=2e-5, linf=5e-5), label="c4 f32+mlp")
+    # and the network form stays close to the table form of the same run
+    p3 = I.make_c3(nr=48, nth=24, nph=48, dt=4.0e-5)
+    tab_run, _ = run_gpu(p3, "f32", 50)
+    errs = rel_errors(got, tab_run)
+    say("  mlp vs table: " + " ".join(f"{k}:{v[0]:.1e}/{v[1]:.1e}" for k, v in errs.items()))
+    assert max(v[0] for v in errs.values()) < 1e-3
