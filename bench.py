@@ -1,0 +1,199 @@
+"""Benchmark of the M1 radiation step on one MI355X.
+
+Headline: cell updates/s of one step (m1_step_explicit + m1_step_implicit)
+on the spherical 192x96x192 workload with FP32 transport, the FP64
+implicit solve and the GPU-trained MLP opacity surrogate; the plain FP64
+form and the other forms are timed beside it.  Inputs are synthetic and
+resident in device memory before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only]
+
+Prints one JSON line.  --only times the headline form alone (used under
+rocprofv3).  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kernel, precision, opacity_kind):
+    """Bytes each kernel must move per cell: every field read once and
+    written once (ghost re-reads excluded), gas in FP64, radiation and the
+    opacity cache in the form's precision."""
+    s = 4 if precision == "f32" else 8
+    if kernel == "transport":
+        return 4 * s + s + 4 * s                 # E,F in; tau in; E*,F* out
+    cache = 0 if opacity_kind == "const" else 4 * s   # rho kP, tau in and out
+    return 4 * s + 40 + 4 * s + 32 + cache      # E*,F* in; rho,m,Eg in; E,F out; m,Eg out
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--only", action="store_true", help="time the headline form only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--train-steps", type=int, default=30000)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def train_surrogate(m1, I, torch, solver, steps):
+    ntr, nev = 1_000_000, 100_000
+    import numpy as np
+    smp = np.concatenate([I.mlp_samples(ntr, 4), I.mlp_samples(nev, 5)])
+    dsmp = torch.from_numpy(smp).to("cuda")
+    rep = m1.m1_mlp_train(solver.ctx, dsmp, ntr, nev, I.mlp_init(7), batch=1024, steps=steps,
+                          lr=2e-3, lr_final=2e-6)
+    return rep
+
+
+def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None):
+    """Returns dict with cells/s and per-kernel average durations."""
+    mlp = None
+    if prob.opacity["kind"] == 3:
+        # construct with the table, then train the surrogate in place
+        tab_prob = prob
+        tab_prob.opacity = dict(prob.opacity, kind=2)
+        s = m1.Solver(tab_prob, precision=precision)
+        rep = train_surrogate(m1, I, torch, s, mlp_train_steps)
+        tab_prob.opacity["kind"] = 3
+        log(f"  surrogate trained: {rep}")
+        mlp = rep
+    else:
+        s = m1.Solver(prob, precision=precision)
+    dt = prob.dt
+    stream = s.stream
+    for _ in range(W):
+        s.step(dt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        m1.m1_step_explicit(s.ctx, dt)
+        m1.m1_step_implicit(s.ctx, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # per-kernel durations: events around each launch on the launch stream
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    for k in range(K):
+        ev[k][0].record(stream)
+        m1.m1_step_explicit(s.ctx, dt)
+        ev[k][1].record(stream)
+        m1.m1_step_implicit(s.ctx, dt)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    t_tr = sum(ev[k][0].elapsed_time(ev[k][1]) for k in range(K)) / K
+    t_im = sum(ev[k][1].elapsed_time(ev[k][2]) for k in range(K)) / K
+    d = s.diagnostics()
+    s.close()
+    n = prob.ncells
+    return dict(cells_per_s=n * K / (ms * 1e-3), ms_per_step=ms / K, wall_s=wall,
+                transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp)
+
+
+def oracle_baseline(I, seconds_target=15.0):
+    """The FP64 oracle on a bounded sample of the headline workload: the
+    same spherical recipe with the MLP surrogate on a 96x48x96 grid."""
+    import numpy as np
+    from oracle import oracle as orc
+    p = I.make_c4(nr=96, nth=48, nph=96)
+    tab = p.opacity
+    a = tab["log10_kP"].astype(np.float64)
+    b = tab["log10_kR"].astype(np.float64)
+    norm = np.array([a.mean(), a.std(), b.mean(), b.std()])
+    o = orc.Oracle(p, dict(theta=I.mlp_init(7).astype(np.float64), norm=norm, bf16=True))
+    st = p.fields
+    steps, t = 0, 0.0
+    while t < seconds_target and steps < 20:
+        t0 = time.perf_counter()
+        st, _ = o.run(st, p.dt, 1)
+        t += time.perf_counter() - t0
+        steps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=p.ncells * steps / t, unit="cell updates/s", cores=cores, kind="oracle",
+                sample=f"spherical recipe with MLP opacity on 96x48x96 cells, {steps} steps, {t:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2606_26268_amd import inputs as I
+    from paper_2606_26268_amd import m1
+    K, W = args.steps, args.warmup
+
+    log("headline: spherical 192x96x192, f32 transport + f64 implicit + MLP opacity")
+    head = time_form(m1, torch, I.make_c4(), "f32", K, W, args.train_steps, I)
+    forms = {"c4_f32_mlp": head}
+    if not args.only:
+        for name, mk, prec in (("c3_f32_table", I.make_c3, "f32"), ("c3_p64_table", I.make_c3, "p64"),
+                               ("c1_p64_const", I.make_c1, "p64"), ("c1_f32_const", I.make_c1, "f32"),
+                               ("c2_p64_const", I.make_c2, "p64"), ("c2_f32_const", I.make_c2, "f32")):
+            log(f"form {name}")
+            forms[name] = time_form(m1, torch, mk(), prec, K, W)
+
+    ncell = 192 * 96 * 192
+    kern = "transport" if head["transport_ms"] >= head["implicit_ms"] else "implicit"
+    kms = head["transport_ms"] if kern == "transport" else head["implicit_ms"]
+    bytes_per_launch = algorithmic_bytes(kern, "f32", "mlp") * ncell
+    achieved = bytes_per_launch / (kms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kern)
+
+    out_forms = {}
+    for name, r in forms.items():
+        prec = "f32" if "f32" in name else "p64"
+        kind = "const" if "const" in name else "table"
+        bps = algorithmic_bytes("transport", prec, kind) + algorithmic_bytes("implicit", prec, kind)
+        out_forms[name] = dict(cells_per_s=r["cells_per_s"], ms_per_step=r["ms_per_step"],
+                               transport_ms=r["transport_ms"], implicit_ms=r["implicit_ms"],
+                               bytes_per_cell_step=bps,
+                               hbm_frac=r["cells_per_s"] * bps / (HBM_PEAK_GBS * 1e9),
+                               fixups=r["counters"][:3])
+    cpu = None if args.no_cpu else oracle_baseline(I)
+    line = {
+        "metric": "M1 cell updates/s (explicit+implicit), FP32/MLP form vs FP64 plain, 1 MI355X",
+        "value": head["cells_per_s"],
+        "unit": "cell updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 transport / f64 implicit / bf16-mfma mlp",
+        "data": "synthetic",
+        "config": {"workload": "spherical 192x96x192 log-r grid, perturbed r^-2 density, r^-1/2 T, "
+                               "FP32 transport + FP64 implicit + MLP opacity (100-step run)",
+                   "cells": ncell},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": out_forms,
+        "mlp_training": head["mlp"],
+        "context": {"paper_rmhd_cell_updates_per_s_per_mi250x_node": 7.6e8},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -8,12 +8,17 @@
 
 namespace m1 {
 
+// Arithmetic primitives per precision: the FP64 form keeps IEEE division and
+// square root; the FP32 form uses the hardware reciprocal and square root
+// (about 1 ulp), well inside its 1e-5 tolerance.
 template <typename R> struct Num;
 template <> struct Num<double> {
     static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 };
 template <> struct Num<float> {
-    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 };
 
 // Closure quantities of one radiation state (E, F) seen from direction d:
@@ -112,6 +117,116 @@ __device__ __forceinline__ void ffix(R U[4], const R C[4])
     } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) U[q] = C[q];
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Face-flux building blocks with a run-time direction (used by the tiled
+// kernel, where one wavefront mixes x and y faces).  Same mathematics as
+// closure_wave / hll_flux / ffix, arranged to need four reciprocals and two
+// square roots per state: with E^-1, |F|^-2 and s = sqrt(4 - 3 f^2),
+//   f mu = F_d / E (unclamped f) or F_d / |F| (f clamped to 1),
+//   n_i n_d = F_i F_d / |F|^2,  lambda_-+ = (f mu -+ zeta) / s.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ Wave<R> closure_wave_rt(R E, R Fx, R Fy, R Fz, int d)
+{
+    Wave<R> w;
+    const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const R iE = Num<R>::rcp(E);
+    R f2 = F2 * iE * iE;
+    const bool clamped = f2 > R(1);
+    f2 = clamped ? R(1) : f2;
+    const R s = Num<R>::sqrt_(R(4) - R(3) * f2);
+    const R xi = (R(3) + R(4) * f2) * Num<R>::rcp(R(5) + R(2) * s);
+    const R iF2 = F2 > R(0) ? Num<R>::rcp(F2) : R(0);
+    const R Fd = d == 0 ? Fx : (d == 1 ? Fy : Fz);
+    const R mu2 = Fd * Fd * iF2;
+    R z2 = (R(2) / R(3)) * (R(4) - R(3) * f2 - s) + R(2) * mu2 * (R(2) - f2 - s);
+    z2 = z2 < R(0) ? R(0) : z2;
+    const R zeta = Num<R>::sqrt_(z2);
+    const R fmu = clamped ? Fd * Num<R>::sqrt_(iF2) : Fd * iE;
+    const R is = Num<R>::rcp(s);
+    w.lm = (fmu - zeta) * is;
+    w.lp = (fmu + zeta) * is;
+    const R iso = R(0.5) * (R(1) - xi) * E;
+    const R c = R(0.5) * (R(3) * xi - R(1)) * E * iF2 * Fd;
+    w.phi[0] = Fd;
+    w.phi[1] = c * Fx + (d == 0 ? iso : R(0));
+    w.phi[2] = c * Fy + (d == 1 ? iso : R(0));
+    w.phi[3] = c * Fz + (d == 2 ? iso : R(0));
+    return w;
+}
+
+// f-preserving fix with squared norms: with r = E_f / E_c, keep F_face iff
+// |F_f|^2 <= E_f^2 and |F_f|^2 > |F_c|^2 r^2 (E > 0), i.e. f_face <= 1 and
+// f_face > f_centre; otherwise F_face = r F_centre.
+template <typename R>
+__device__ __forceinline__ void ffix_sq(R U[4], const R C[4])
+{
+    if (U[0] > R(0)) {
+        const R Ff2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+        const R Fc2 = C[1] * C[1] + C[2] * C[2] + C[3] * C[3];
+        const R r = U[0] * Num<R>::rcp(C[0]);
+        const bool keep = Ff2 <= U[0] * U[0] && Ff2 > Fc2 * (r * r);
+        if (!keep) {
+            U[1] = C[1] * r;
+            U[2] = C[2] * r;
+            U[3] = C[3] * r;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) U[q] = C[q];
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R vanleer_fast(R dl, R dr)
+{
+    const R p = dl * dr;
+    return p > R(0) ? (R(2) * p) * Num<R>::rcp(dl + dr) : R(0);
+}
+
+// HLL flux c_hat Phi* at the face between cells t-1 and t along d from the
+// stencil q(t-2), q(t-1), q(t), q(t+1): PLM van Leer slopes of the two donor
+// cells (w* = inverse centre spacings, hp/hm = centre-to-face offsets), the
+// f-preserving fix, both closures, the optical-depth-limited HLL speeds.
+template <typename R>
+__device__ __forceinline__ void face_flux(int d, const R qa[4], const R qb[4], const R qc[4], const R qd[4],
+                                          R wA, R wB, R wC, R hpL, R hmR, R tauL, R tauR, R c_hat, R out[4])
+{
+    R UL[4], UR[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const R dAB = (qb[v] - qa[v]) * wA;
+        const R dBC = (qc[v] - qb[v]) * wB;
+        const R dCD = (qd[v] - qc[v]) * wC;
+        UL[v] = qb[v] + vanleer_fast(dAB, dBC) * hpL;
+        UR[v] = qc[v] - vanleer_fast(dBC, dCD) * hmR;
+    }
+    ffix_sq(UL, qb);
+    ffix_sq(UR, qc);
+    const Wave<R> wl = closure_wave_rt(UL[0], UL[1], UL[2], UL[3], d);
+    const Wave<R> wr = closure_wave_rt(UR[0], UR[1], UR[2], UR[3], d);
+    R lamL = wl.lm < wr.lm ? wl.lm : wr.lm;
+    R lamR = wl.lp > wr.lp ? wl.lp : wr.lp;
+    const R tau = R(0.5) * (tauL + tauR);
+    if (tau > R(0)) {
+        const R lim = R(4) / (R(3) * tau);
+        lamL = lamL < -lim ? -lim : lamL;
+        lamR = lamR > lim ? lim : lamR;
+    }
+    const R SL = lamL < R(0) ? lamL : R(0);
+    const R SR = lamR > R(0) ? lamR : R(0);
+    if (SR > SL) {
+        const R k = c_hat * Num<R>::rcp(SR - SL);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = k * (SR * wl.phi[q] - SL * wr.phi[q] + SL * SR * (UR[q] - UL[q]));
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = c_hat * R(0.5) * (wl.phi[q] + wr.phi[q]);
     }
 }
 

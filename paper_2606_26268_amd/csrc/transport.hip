@@ -100,32 +100,11 @@ __device__ __forceinline__ void ignorable_div(const TArgs<R> &a, const R U[4], R
     for (int v = 0; v < 4; ++v) acc[v] += dA * w.phi[v];
 }
 
-template <typename R, int NDIM, int GEOM>
-__global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
+// U* = U - dt div(Phi) + dt c_hat S_geo(U), then E >= floor and f <= 1
+// (counted), stored to the transported state.
+template <typename R, int GEOM>
+__device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], const R acc[4], int i, int j, int id)
 {
-    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-    const int N = n0 * n1 * n2;
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N) return;
-    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
-    R U[4];
-    load4(a, id, U);
-    R acc[4] = {R(0), R(0), R(0), R(0)};
-
-    direction_div<R, 0>(a, id - i, 1, i, R(1), acc);
-    if (NDIM >= 2) {
-        const R tr = a.m.trA[1][i];
-        direction_div<R, 1>(a, id - j * n0, n0, j, tr, acc);
-    } else if (a.ign[1]) {
-        ignorable_div<R, 1>(a, U, a.m.trA[1][i], acc);
-    }
-    if (NDIM >= 3) {
-        const R tr = a.m.trA[2][i] * a.m.trB[2][j];
-        direction_div<R, 2>(a, id - k * n0 * n1, n0 * n1, k, tr, acc);
-    } else if (a.ign[2]) {
-        ignorable_div<R, 2>(a, U, a.m.trA[2][i] * a.m.trB[2][j], acc);
-    }
-
     R Us[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) Us[v] = U[v] - a.dt * acc[v];
@@ -175,6 +154,186 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
     for (int v = 0; v < 4; ++v) a.out[v][id] = Us[v];
 }
 
+template <typename R, int NDIM, int GEOM>
+__global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
+{
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const int N = n0 * n1 * n2;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    R U[4];
+    load4(a, id, U);
+    R acc[4] = {R(0), R(0), R(0), R(0)};
+
+    direction_div<R, 0>(a, id - i, 1, i, R(1), acc);
+    if (NDIM >= 2) {
+        const R tr = a.m.trA[1][i];
+        direction_div<R, 1>(a, id - j * n0, n0, j, tr, acc);
+    } else if (a.ign[1]) {
+        ignorable_div<R, 1>(a, U, a.m.trA[1][i], acc);
+    }
+    if (NDIM >= 3) {
+        const R tr = a.m.trA[2][i] * a.m.trB[2][j];
+        direction_div<R, 2>(a, id - k * n0 * n1, n0 * n1, k, tr, acc);
+    } else if (a.ign[2]) {
+        ignorable_div<R, 2>(a, U, a.m.trA[2][i] * a.m.trB[2][j], acc);
+    }
+
+    finish_cell<R, GEOM>(a, U, acc, i, j, id);
+}
+
+// ---------------------------------------------------------------------------
+// 3D tiled kernel: a block owns a TX x TY column of cells and marches along z
+// over a chunk of planes.  Per plane the state with a two-cell halo in x and
+// y is staged in LDS, every x and y face of the tile is computed once (one
+// face per thread per pass, faces of both directions in one flat loop), the
+// z face above the plane comes from a per-thread register window of four
+// planes, and the face fluxes are exchanged through LDS for the update.
+// ---------------------------------------------------------------------------
+constexpr int TX = 32, TY = 8, HX = TX + 4, HY = TY + 4, NT = TX * TY;
+constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX, NHALO = 2 * (2 * TY + 2 * TX);
+
+template <typename R, int GEOM>
+__global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
+{
+    __shared__ R sq[4][HY][HX];
+    __shared__ R st[HY][HX];
+    __shared__ R sfx[4][TY][TX + 1];
+    __shared__ R sfy[4][TY + 1][TX];
+
+    // consecutive logical tiles share an XCD (blocks are dealt to XCDs round-robin)
+    const int per = (nblocks + 7) / 8;
+    const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblocks) return;
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const int tx_i = L % tiles_x, rest = L / tiles_x;
+    const int x0 = tx_i * TX, y0 = (rest % tiles_y) * TY, z0 = (rest / tiles_y) * nz_chunk;
+    const int z1 = min(z0 + nz_chunk, n2);
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int i = x0 + lx, j = y0 + ly;
+    const bool live = i < n0 && j < n1;
+    const int mi = map_index(i, n0, a.bc[0][0], a.bc[0][1]);
+    const int mj = map_index(j, n1, a.bc[1][0], a.bc[1][1]);
+    const int plane = n0 * n1;
+    const int col = mj * n0 + mi;
+
+    // halo cell of this thread (tid < NHALO): cross-shaped, no corners
+    int hx = 0, hy = 0, hcol = 0;
+    if (tid < NHALO) {
+        if (tid < 2 * TX) { hy = tid / TX; hx = 2 + tid % TX; }
+        else if (tid < 4 * TX) { hy = TY + 2 + (tid - 2 * TX) / TX; hx = 2 + (tid - 2 * TX) % TX; }
+        else if (tid < 4 * TX + 2 * TY) { hx = (tid - 4 * TX) / TY; hy = 2 + (tid - 4 * TX) % TY; }
+        else { hx = TX + 2 + (tid - 4 * TX - 2 * TY) / TY; hy = 2 + (tid - 4 * TX - 2 * TY) % TY; }
+        const int gi = map_index(x0 - 2 + hx, n0, a.bc[0][0], a.bc[0][1]);
+        const int gj = map_index(y0 - 2 + hy, n1, a.bc[1][0], a.bc[1][1]);
+        hcol = gj * n0 + gi;
+    }
+
+    const int bz0 = a.bc[2][0], bz1 = a.bc[2][1];
+    auto zlin = [&](int kk, int c) { return map_index(kk, n2, bz0, bz1) * plane + c; };
+    const R *wz = a.m.winv[2], *hpz = a.m.hp[2], *hmz = a.m.hm[2];
+
+    // register window of the thread's column: planes k-1 .. k+2
+    R W[4][4], T1, T2, Fzlo[4], Fzhi[4];
+    {
+        R Q0[4];
+        load4(a, zlin(z0 - 2, col), Q0);
+        load4(a, zlin(z0 - 1, col), W[0]);
+        load4(a, zlin(z0, col), W[1]);
+        load4(a, zlin(z0 + 1, col), W[2]);
+        load4(a, zlin(z0 + 2, col), W[3]);
+        const R Tm = a.tau[zlin(z0 - 1, col)];
+        T1 = a.tau[zlin(z0, col)];
+        T2 = a.tau[zlin(z0 + 1, col)];
+        face_flux<R>(2, Q0, W[0], W[1], W[2], wz[z0 + 1], wz[z0 + 2], wz[z0 + 3], hpz[z0 + 1], hmz[z0 + 2],
+                     Tm, T1, a.c_hat, Fzlo);
+    }
+
+    for (int k = z0; k < z1; ++k) {
+        // prefetch the plane entering the window and this plane's halo
+        R Qn[4];
+        load4(a, zlin(k + 3, col), Qn);
+        const R Tn = a.tau[zlin(k + 2, col)];
+        R Hq[4], Ht = R(0);
+        if (tid < NHALO) {
+            load4(a, k * plane + hcol, Hq);
+            Ht = a.tau[k * plane + hcol];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sq[v][ly + 2][lx + 2] = W[1][v];
+        st[ly + 2][lx + 2] = T1;
+        if (tid < NHALO) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sq[v][hy][hx] = Hq[v];
+            st[hy][hx] = Ht;
+        }
+        __syncthreads();
+
+        // x faces (left face of column f) and y faces (lower face of row g)
+        for (int q = tid; q < NXF + NYF; q += NT) {
+            int d, r0, c0, dr, dc, gidx;
+            if (q < NXF) {
+                const int row = q / (TX + 1), fo = q % (TX + 1);
+                gidx = x0 + fo;
+                if (gidx > n0 || y0 + row >= n1) continue;
+                d = 0; r0 = row + 2; c0 = fo; dr = 0; dc = 1;
+            } else {
+                const int qq = q - NXF, go = qq / TX, cl = qq % TX;
+                gidx = y0 + go;
+                if (gidx > n1 || x0 + cl >= n0) continue;
+                d = 1; r0 = go; c0 = cl + 2; dr = 1; dc = 0;
+            }
+            R qs[4][4], tl, tr;
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) qs[s2][v] = sq[v][r0 + s2 * dr][c0 + s2 * dc];
+            tl = st[r0 + dr][c0 + dc];
+            tr = st[r0 + 2 * dr][c0 + 2 * dc];
+            const R *wv = a.m.winv[d], *hpv = a.m.hp[d], *hmv = a.m.hm[d];
+            R fl[4];
+            face_flux<R>(d, qs[0], qs[1], qs[2], qs[3], wv[gidx + 1], wv[gidx + 2], wv[gidx + 3], hpv[gidx + 1],
+                         hmv[gidx + 2], tl, tr, a.c_hat, fl);
+            if (d == 0) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sfx[v][r0 - 2][c0] = fl[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sfy[v][r0][c0 - 2] = fl[v];
+            }
+        }
+        // z face above the plane from the register window
+        face_flux<R>(2, W[0], W[1], W[2], W[3], wz[k + 2], wz[k + 3], wz[k + 4], hpz[k + 2], hmz[k + 3], T1, T2,
+                     a.c_hat, Fzhi);
+        __syncthreads();
+
+        if (live) {
+            R acc[4];
+            const R axl = a.m.alo[0][i], axh = a.m.ahi[0][i];
+            const R tr1 = a.m.trA[1][i];
+            const R ayl = a.m.alo[1][j] * tr1, ayh = a.m.ahi[1][j] * tr1;
+            const R tr2 = a.m.trA[2][i] * a.m.trB[2][j];
+            const R azl = a.m.alo[2][k] * tr2, azh = a.m.ahi[2][k] * tr2;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[v] = (axh * sfx[v][ly][lx + 1] - axl * sfx[v][ly][lx]) +
+                         (ayh * sfy[v][ly + 1][lx] - ayl * sfy[v][ly][lx]) + (azh * Fzhi[v] - azl * Fzlo[v]);
+            finish_cell<R, GEOM>(a, W[1], acc, i, j, (k * n1 + j) * n0 + i);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            Fzlo[v] = Fzhi[v];
+            W[0][v] = W[1][v];
+            W[1][v] = W[2][v];
+            W[2][v] = W[3][v];
+            W[3][v] = Qn[v];
+        }
+        T1 = T2;
+        T2 = Tn;
+    }
+}
+
 template <typename R>
 static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
 {
@@ -197,6 +356,29 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
     a.e_floor = R(c->par.e_floor);
     a.cnt = c->cnt;
     const int N = c->n[0] * c->n[1] * c->n[2];
+    if (c->ndim == 3) {
+        const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
+        // planes per block: enough blocks to fill the chip several times over
+        int nz = 64;
+        while (nz > 4 && (long)tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz) < 2048) nz /= 2;
+        const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
+        const int launched = ((nblocks + 7) / 8) * 8;
+        switch (c->geom) {
+        case M1_CARTESIAN:
+            hipLaunchKernelGGL((k_transport3d<R, M1_CARTESIAN>), dim3(launched), dim3(NT), 0, c->stream, a, nz,
+                               tiles_x, tiles_y, nblocks);
+            break;
+        case M1_CYLINDRICAL:
+            hipLaunchKernelGGL((k_transport3d<R, M1_CYLINDRICAL>), dim3(launched), dim3(NT), 0, c->stream, a, nz,
+                               tiles_x, tiles_y, nblocks);
+            break;
+        default:
+            hipLaunchKernelGGL((k_transport3d<R, M1_SPHERICAL>), dim3(launched), dim3(NT), 0, c->stream, a, nz,
+                               tiles_x, tiles_y, nblocks);
+            break;
+        }
+        return hipGetLastError();
+    }
     dim3 block(256), grid((N + 255) / 256);
 #define M1_LAUNCH(ND, G) \
     hipLaunchKernelGGL((k_transport<R, ND, G>), grid, block, 0, c->stream, a)
@@ -206,10 +388,10 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
     case M1_CYLINDRICAL: M1_LAUNCH(ND, M1_CYLINDRICAL); break;            \
     default: M1_LAUNCH(ND, M1_SPHERICAL); break;                          \
     }
-    switch (c->ndim) {
-    case 1: M1_GEOMS(1); break;
-    case 2: M1_GEOMS(2); break;
-    default: M1_GEOMS(3); break;
+    if (c->ndim == 1) {
+        M1_GEOMS(1);
+    } else {
+        M1_GEOMS(2);
     }
 #undef M1_GEOMS
 #undef M1_LAUNCH

@@ -227,8 +227,8 @@ def m1_mlp_gradient(ctx, samples_dev, n, theta):
     return loss.value, g
 
 
-def m1_opacity_eval(ctx, rho, T, kP, kR):
-    n = rho.numel()
+def m1_opacity_eval(ctx, n, rho, T, kP, kR):
+    assert rho.numel() >= n and T.numel() >= n and kP.numel() >= n and kR.numel() >= n
     _check(lib().m1_opacity_eval(ctx, n, C.c_void_p(rho.data_ptr()), C.c_void_p(T.data_ptr()),
                                  C.c_void_p(kP.data_ptr()), C.c_void_p(kR.data_ptr())))
 

@@ -28,6 +28,32 @@ def rel_errors(got, ref, fields=ALL):
     return out
 
 
+def assert_close_f32(got, ref, fields=ALL, label="", gas_scale=1.0):
+    """FP32 transport vs the FP64 oracle.
+
+    rel-L1 <= 1e-5 per field (radiation; gas fields scaled by gas_scale for
+    c >> c_hat, where E_g absorbs (c/c_hat) times the FP32 rounding of E).
+    The f-preserving face fix is discontinuous, so rounding-level
+    differences flip a few face decisions; the L-infinity excess must stay
+    confined to those cells: at most 1e-3 of the cells above 1e-5 max|ref|
+    and rel-L-infinity <= 1e-2.
+    """
+    errs = rel_errors(got, ref, fields)
+    n = got[fields[0]].size
+    flips = {}
+    for k in fields:
+        d = np.abs(got[k] - ref[k])
+        flips[k] = int((d > 1e-5 * np.abs(ref[k]).max()).sum())
+    say(f"  {label} " + " ".join(f"{k}:{v[0]:.1e}/{v[1]:.1e}/{flips[k]}" for k, v in errs.items()))
+    bad = {}
+    for k, (l1, linf) in errs.items():
+        scale = gas_scale if k in ("mx", "my", "mz", "Eg") else 1.0
+        if l1 > 1e-5 * scale or linf > 1e-2 * scale or flips[k] > max(2, 1e-3 * n) * scale:
+            bad[k] = (l1, linf, flips[k])
+    assert not bad, f"{label} FP32 parity failed: {bad}"
+    return errs, flips
+
+
 def assert_close(got, ref, tol, fields=ALL, label=""):
     errs = rel_errors(got, ref, fields)
     bad = {k: v for k, v in errs.items() if v[0] > tol["l1"] or v[1] > tol["linf"]}
