@@ -135,8 +135,9 @@ __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwave = (gridDim.x * blockDim.x) >> 6;
-    MlpWave net;
-    net.load(a.op.mlp, lane);
+    __shared__ MlpShared sh;
+    mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
+    __syncthreads();
     for (int base = wave * 64; base < N; base += nwave * 64) {
         const int id = base + lane;
         const bool live = id < N;
@@ -146,7 +147,7 @@ __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
         if (live) T1 = implicit_cell<R, false>(a, id, i, j, k);
         const float rho = float(a.rho[idc]);
         float kP, kR;
-        net.opacity(a.op, rho, float(T1), lane, kP, kR);
+        mlp_opacity_shared(a.op, sh, rho, float(T1), lane, kP, kR);
         if (live) {
             a.rkp[id] = R(rho * kP);
             a.tau[id] = R(rho * (kR + float(a.op.sigma))) * cell_hmax(a.m, a.ndim, i, j, k);
@@ -192,7 +193,7 @@ static int mlp_grid(int N)
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
     }
     const int chunks = (N + 63) / 64;
-    int blocks = cus * 8;                       // 4 waves per block, 32 waves per CU
+    int blocks = cus * 8;                       // 4 waves per block, up to 32 waves per CU
     const int need = (chunks + 3) / 4;
     return need < blocks ? (need > 0 ? need : 1) : blocks;
 }
@@ -249,8 +250,9 @@ __global__ void __launch_bounds__(256) k_opacity_init_mlp(IArgs<R> a)
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwave = (gridDim.x * blockDim.x) >> 6;
-    MlpWave net;
-    net.load(a.op.mlp, lane);
+    __shared__ MlpShared sh;
+    mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
+    __syncthreads();
     for (int base = wave * 64; base < N; base += nwave * 64) {
         const int id = base + lane;
         const bool live = id < N;
@@ -259,7 +261,7 @@ __global__ void __launch_bounds__(256) k_opacity_init_mlp(IArgs<R> a)
         const double T = gas_T(a.rho[idc], a.mx[idc], a.my[idc], a.mz[idc], a.Eg[idc], a.k.gamma);
         const float rho = float(a.rho[idc]);
         float kP, kR;
-        net.opacity(a.op, rho, float(T), lane, kP, kR);
+        mlp_opacity_shared(a.op, sh, rho, float(T), lane, kP, kR);
         if (live) {
             a.rkp[id] = R(rho * kP);
             a.tau[id] = R(rho * (kR + float(a.op.sigma))) * cell_hmax(a.m, a.ndim, i, j, k);
@@ -313,14 +315,15 @@ __global__ void __launch_bounds__(256) k_opacity_eval_mlp(OpacityParams op, long
     const int lane = threadIdx.x & 63;
     const long wave = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
     const long nwave = (gridDim.x * (long)blockDim.x) >> 6;
-    MlpWave net;
-    net.load(op.mlp, lane);
+    __shared__ MlpShared sh;
+    mlp_stage(op.mlp, sh, threadIdx.x, blockDim.x);
+    __syncthreads();
     for (long base = wave * 64; base < n; base += nwave * 64) {
         const long id = base + lane;
         const bool live = id < n;
         const long idc = live ? id : n - 1;
         float a, b;
-        net.opacity(op, float(rho[idc]), float(T[idc]), lane, a, b);
+        mlp_opacity_shared(op, sh, float(rho[idc]), float(T[idc]), lane, a, b);
         if (live) {
             kP[id] = a;
             kR[id] = b;

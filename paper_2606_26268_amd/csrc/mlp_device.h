@@ -174,4 +174,107 @@ struct MlpWave {
     }
 };
 
+
+// ---------------------------------------------------------------------------
+// Inference variant with the 64x64 layer's operands staged in LDS once per
+// block and the first layer evaluated just in time, 16 units per k-step, so
+// a wavefront keeps only the 64 accumulators and one 16-unit chunk live.
+// ---------------------------------------------------------------------------
+
+struct MlpShared {
+    bf16x8 w2[2][2][4][64];   // [hi, lo][mt][ks][lane], 16 KiB
+};
+
+__device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, int tid, int nthreads)
+{
+    const bf16x8 *hi = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_W2HI);
+    const bf16x8 *lo = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_W2LO);
+    bf16x8 *dst = &sh.w2[0][0][0][0];
+    for (int q = tid; q < 512; q += nthreads) {
+        dst[q] = hi[q];
+        dst[512 + q] = lo[q];
+    }
+}
+
+__device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShared &sh, float x0, float x1, int lane,
+                                                   float &y0, float &y1)
+{
+    const int g = lane >> 5;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[mt][nt][i] = 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        float h[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int u = 16 * ks + e;
+            h[e] = fast_tanh(p[MLP_OFF_W1 + 2 * u] * x0 + p[MLP_OFF_W1 + 2 * u + 1] * x1 + p[MLP_OFF_B1 + u]);
+        }
+        bf16x8 own_h, own_l, oth_h, oth_l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float mine = g ? h[8 + e] : h[e];
+            const float send = g ? h[e] : h[8 + e];
+            const float recv = __shfl_xor(send, 32);
+            const __bf16 mh = to_bf16(mine), rh = to_bf16(recv);
+            own_h[e] = mh;
+            own_l[e] = to_bf16(mine - float(mh));
+            oth_h[e] = rh;
+            oth_l[e] = to_bf16(recv - float(rh));
+        }
+        const bf16x8 b0h = g == 0 ? own_h : oth_h, b0l = g == 0 ? own_l : oth_l;
+        const bf16x8 b1h = g == 1 ? own_h : oth_h, b1l = g == 1 ? own_l : oth_l;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const bf16x8 ah = sh.w2[0][mt][ks][lane], al = sh.w2[1][mt][ks][lane];
+            acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b0h, acc[mt][0], 0, 0, 0);
+            acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b0l, acc[mt][0], 0, 0, 0);
+            acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b0h, acc[mt][0], 0, 0, 0);
+            acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b1h, acc[mt][1], 0, 0, 0);
+            acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b1l, acc[mt][1], 0, 0, 0);
+            acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b1h, acc[mt][1], 0, 0, 0);
+        }
+    }
+    float part[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            // unit of this slot for lane group 0 / 1: uniform loads, then a select
+            const int u0 = MlpWave::unit(mt, i, 0), u1 = u0 + 4;
+            const float bb = g ? p[MLP_OFF_B2 + u1] : p[MLP_OFF_B2 + u0];
+            const float w0 = g ? p[MLP_OFF_W3 + u1] : p[MLP_OFF_W3 + u0];
+            const float w1 = g ? p[MLP_OFF_W3 + 64 + u1] : p[MLP_OFF_W3 + 64 + u0];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const float h2 = fast_tanh(acc[mt][nt][i] + bb);
+                part[nt][0] += w0 * h2;
+                part[nt][1] += w1 * h2;
+            }
+        }
+    const float s0 = g ? part[0][0] : part[1][0];
+    const float s1 = g ? part[0][1] : part[1][1];
+    const float r0 = __shfl_xor(s0, 32), r1 = __shfl_xor(s1, 32);
+    const float m0 = g ? part[1][0] : part[0][0];
+    const float m1 = g ? part[1][1] : part[0][1];
+    y0 = m0 + r0 + p[MLP_OFF_B3] + p[MLP_OFF_WS] * x0 + p[MLP_OFF_WS + 1] * x1;
+    y1 = m1 + r1 + p[MLP_OFF_B3 + 1] + p[MLP_OFF_WS + 2] * x0 + p[MLP_OFF_WS + 3] * x1;
+}
+
+__device__ __forceinline__ void mlp_opacity_shared(const OpacityParams &op, const MlpShared &sh, float rho, float T,
+                                                   int lane, float &kP, float &kR)
+{
+    const float *p = op.mlp;
+    float x0, x1, y0, y1;
+    MlpWave::inputs(op, rho, T, x0, x1);
+    mlp_forward_shared(p, sh, x0, x1, lane, y0, y1);
+    kP = exp10f(y0 * p[MLP_OFF_NORM + 1] + p[MLP_OFF_NORM + 0]);
+    kR = exp10f(y1 * p[MLP_OFF_NORM + 3] + p[MLP_OFF_NORM + 2]);
+}
+
 } // namespace m1
