@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--only", action="store_true", help="time the headline form only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--train-steps", type=int, default=30000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -108,6 +110,41 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None):
                 transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp)
 
 
+def source_hash(kernel):
+    """sha256 of the translation unit a kernel is built from (and its headers)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2606_26268_amd", "csrc")
+    files = {"transport": ["transport.hip", "m1_device.h"],
+             "implicit": ["implicit.hip", "opacity_device.h", "mlp_device.h"]}[kernel]
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter runs (profiles/
+    traffic.json), or None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(f"{kernel}:{workload}")
+    if not rec or rec.get("source") != source_hash(kernel):
+        return None
+    return rec["bytes_per_launch"]
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28                       # 2^28 float32 = 1 GiB read + 1 GiB written
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
 def oracle_baseline(I, seconds_target=15.0):
     """The FP64 oracle on a bounded sample of the headline workload: the
     same spherical recipe with the MLP surrogate on a 96x48x96 grid."""
@@ -133,6 +170,9 @@ def oracle_baseline(I, seconds_target=15.0):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -157,7 +197,8 @@ def main():
     bytes_per_launch = algorithmic_bytes(kern, "f32", "mlp") * ncell
     achieved = bytes_per_launch / (kms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kern)
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kern, "c4_f32_mlp"),
+                    kernel=kern, ms_per_launch=kms, algorithmic_bytes_per_launch=bytes_per_launch)
 
     out_forms = {}
     for name, r in forms.items():

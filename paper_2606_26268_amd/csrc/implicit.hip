@@ -126,20 +126,19 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
 }
 
 // MLP opacity: every lane of a wavefront takes part in the network
-// evaluation, so the grid strides over 64-cell chunks without early exits.
+// evaluation (one 64-cell chunk per wavefront), so lanes past the last cell
+// compute on a clamped index instead of exiting early.
 template <typename R>
 __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
 {
     const int n0 = a.n[0], n1 = a.n[1];
     const int N = n0 * n1 * a.n[2];
     const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwave = (gridDim.x * blockDim.x) >> 6;
     __shared__ MlpShared sh;
     mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
     __syncthreads();
-    for (int base = wave * 64; base < N; base += nwave * 64) {
-        const int id = base + lane;
+    {
+        const int id = blockIdx.x * blockDim.x + threadIdx.x;
         const bool live = id < N;
         const int idc = live ? id : N - 1;
         const int i = idc % n0, j = (idc / n0) % n1, k = idc / (n0 * n1);
@@ -185,19 +184,6 @@ static void fill_args(m1_ctx *c, IArgs<R> &a, const Metric<R> &met, double dt)
     a.cnt = c->cnt;
 }
 
-static int mlp_grid(int N)
-{
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
-    }
-    const int chunks = (N + 63) / 64;
-    int blocks = cus * 8;                       // 4 waves per block, up to 32 waves per CU
-    const int need = (chunks + 3) / 4;
-    return need < blocks ? (need > 0 ? need : 1) : blocks;
-}
-
 template <typename R>
 static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met)
 {
@@ -210,7 +196,7 @@ static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met)
     case OPK_POWERLAW: hipLaunchKernelGGL((k_implicit<R, OPK_POWERLAW>), grid, block, 0, c->stream, a); break;
     case OPK_TABLE: hipLaunchKernelGGL((k_implicit<R, OPK_TABLE>), grid, block, 0, c->stream, a); break;
     default:
-        hipLaunchKernelGGL((k_implicit_mlp<R>), dim3(mlp_grid(N)), block, 0, c->stream, a);
+        hipLaunchKernelGGL((k_implicit_mlp<R>), grid, block, 0, c->stream, a);
         break;
     }
     return hipGetLastError();
@@ -248,13 +234,11 @@ __global__ void __launch_bounds__(256) k_opacity_init_mlp(IArgs<R> a)
     const int n0 = a.n[0], n1 = a.n[1];
     const int N = n0 * n1 * a.n[2];
     const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwave = (gridDim.x * blockDim.x) >> 6;
     __shared__ MlpShared sh;
     mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
     __syncthreads();
-    for (int base = wave * 64; base < N; base += nwave * 64) {
-        const int id = base + lane;
+    {
+        const int id = blockIdx.x * blockDim.x + threadIdx.x;
         const bool live = id < N;
         const int idc = live ? id : N - 1;
         const int i = idc % n0, j = (idc / n0) % n1, k = idc / (n0 * n1);
@@ -281,7 +265,7 @@ static hipError_t launch_init(m1_ctx *c, const Metric<R> &met)
     case OPK_POWERLAW: hipLaunchKernelGGL((k_opacity_init<R, OPK_POWERLAW>), grid, block, 0, c->stream, a); break;
     case OPK_TABLE: hipLaunchKernelGGL((k_opacity_init<R, OPK_TABLE>), grid, block, 0, c->stream, a); break;
     default:
-        hipLaunchKernelGGL((k_opacity_init_mlp<R>), dim3(mlp_grid(N)), block, 0, c->stream, a);
+        hipLaunchKernelGGL((k_opacity_init_mlp<R>), grid, block, 0, c->stream, a);
         break;
     }
     return hipGetLastError();
@@ -313,13 +297,11 @@ __global__ void __launch_bounds__(256) k_opacity_eval_mlp(OpacityParams op, long
                                                           const double *T, double *kP, double *kR)
 {
     const int lane = threadIdx.x & 63;
-    const long wave = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
-    const long nwave = (gridDim.x * (long)blockDim.x) >> 6;
     __shared__ MlpShared sh;
     mlp_stage(op.mlp, sh, threadIdx.x, blockDim.x);
     __syncthreads();
-    for (long base = wave * 64; base < n; base += nwave * 64) {
-        const long id = base + lane;
+    {
+        const long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
         const bool live = id < n;
         const long idc = live ? id : n - 1;
         float a, b;
@@ -341,13 +323,9 @@ hipError_t launch_opacity_eval(m1_ctx *c, long n, const double *rho, const doubl
     case OPK_CONST: hipLaunchKernelGGL((k_opacity_eval<OPK_CONST>), grid, block, 0, c->stream, c->op, n, rho, T, kP, kR); break;
     case OPK_POWERLAW: hipLaunchKernelGGL((k_opacity_eval<OPK_POWERLAW>), grid, block, 0, c->stream, c->op, n, rho, T, kP, kR); break;
     case OPK_TABLE: hipLaunchKernelGGL((k_opacity_eval<OPK_TABLE>), grid, block, 0, c->stream, c->op, n, rho, T, kP, kR); break;
-    default: {
-        const long chunks = (n + 63) / 64;
-        long blocks = (chunks + 3) / 4;
-        if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(k_opacity_eval_mlp, dim3((unsigned)blocks), block, 0, c->stream, c->op, n, rho, T, kP, kR);
+    default:
+        hipLaunchKernelGGL(k_opacity_eval_mlp, grid, block, 0, c->stream, c->op, n, rho, T, kP, kR);
         break;
-    }
     }
     return hipGetLastError();
 }

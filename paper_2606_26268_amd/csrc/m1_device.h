@@ -8,13 +8,21 @@
 
 namespace m1 {
 
-// Arithmetic primitives per precision: the FP64 form keeps IEEE division and
-// square root; the FP32 form uses the hardware reciprocal and square root
-// (about 1 ulp), well inside its 1e-5 tolerance.
+// Arithmetic primitives per precision.  FP64: IEEE square root; reciprocal
+// from the hardware estimate refined by two Newton steps r <- r (2 - x r)
+// (each doubles the correct bits; the result is within an ulp or two, far
+// inside the 1e-12 parity tolerance; arguments are positive normal numbers).
+// FP32: hardware reciprocal and square root (about 1 ulp), inside 1e-5.
 template <typename R> struct Num;
 template <> struct Num<double> {
     static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rcp(double x)
+    {
+        double r = __builtin_amdgcn_rcp(x);
+        r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+        r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+        return r;
+    }
 };
 template <> struct Num<float> {
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -214,7 +222,7 @@ __device__ __forceinline__ void face_flux(int d, const R qa[4], const R qb[4], c
     R lamR = wl.lp > wr.lp ? wl.lp : wr.lp;
     const R tau = R(0.5) * (tauL + tauR);
     if (tau > R(0)) {
-        const R lim = R(4) / (R(3) * tau);
+        const R lim = R(4) / R(3) * Num<R>::rcp(tau);
         lamL = lamL < -lim ? -lim : lamL;
         lamR = lamR > lim ? lim : lamR;
     }

@@ -113,11 +113,11 @@ __device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], con
         // geometric sources from the cell-centre pressure tensor P = D E
         const R F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
         const R Fn = Num<R>::sqrt_(F2);
-        R f = Fn / U[0];
+        R f = Fn * Num<R>::rcp(U[0]);
         f = f > R(1) ? R(1) : f;
         const R s = Num<R>::sqrt_(R(4) - R(3) * f * f);
-        const R xi = (R(3) + R(4) * f * f) / (R(5) + R(2) * s);
-        const R inv = Fn > R(0) ? R(1) / Fn : R(0);
+        const R xi = (R(3) + R(4) * f * f) * Num<R>::rcp(R(5) + R(2) * s);
+        const R inv = Fn > R(0) ? Num<R>::rcp(Fn) : R(0);
         const R n_[3] = {U[1] * inv, U[2] * inv, U[3] * inv};
         const R iso = R(0.5) * (R(1) - xi) * U[0];
         const R an = R(0.5) * (R(3) * xi - R(1)) * U[0];
@@ -144,7 +144,7 @@ __device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], con
     }
     const R Fn = Num<R>::sqrt_(Us[1] * Us[1] + Us[2] * Us[2] + Us[3] * Us[3]);
     if (Fn > Us[0]) {
-        const R sc = Us[0] / Fn;
+        const R sc = Us[0] * Num<R>::rcp(Fn);
         Us[1] *= sc;
         Us[2] *= sc;
         Us[3] *= sc;
