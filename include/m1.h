@@ -224,6 +224,14 @@ m1_status m1_step_explicit(m1_ctx *ctx, double dt);
  * m1_step_explicit. */
 m1_status m1_step_implicit(m1_ctx *ctx, double dt);
 
+/* Second-order Runge-Kutta step of length dt built from the split step as in
+ * Sect. 2.4 (every sub-step is transport then sources): U1 = S(T(U^n)),
+ * U2 = S(T(U1)), U^{n+1} = (U^n + U2) / 2 for E, F, m and E_g (rho is
+ * frozen), followed by an opacity-cache refresh at the averaged gas state.
+ * Asynchronous.  Allocates its save buffer (the state at t^n) on first use.
+ * M1_ESTATE if no state is bound. */
+m1_status m1_step_rk2(m1_ctx *ctx, double dt);
+
 /* Device pointers of the library's transported state E*, Fx*, Fy*, Fz*
  * (valid after m1_step_explicit; owned by the library). */
 m1_status m1_transported(m1_ctx *ctx, void **E, void **Fx, void **Fy, void **Fz);

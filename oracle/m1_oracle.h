@@ -68,6 +68,8 @@ int m1o_implicit(const m1o_problem *p, double dt, const double *const star[4],
                  double *const st[9], long long cnt[M1O_NCNT]);
 int m1o_run(const m1o_problem *p, double dt, int nsteps, double *const st[9],
             long long cnt[M1O_NCNT]);
+int m1o_run_rk2(const m1o_problem *p, double dt, int nsteps, double *const st[9],
+                long long cnt[M1O_NCNT]);
 
 /* --- single-cell implicit solve (both algebraic forms) -------------------- */
 void m1o_implicit_cell(double Es, double Cv, double T, double kP, double rho, double dt,

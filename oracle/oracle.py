@@ -85,6 +85,7 @@ def lib():
         L.m1o_explicit.argtypes = [C.POINTER(Problem), C.c_double, pp, pp, cnt]
         L.m1o_implicit.argtypes = [C.POINTER(Problem), C.c_double, pp, pp, cnt]
         L.m1o_run.argtypes = [C.POINTER(Problem), C.c_double, C.c_int, pp, cnt]
+        L.m1o_run_rk2.argtypes = [C.POINTER(Problem), C.c_double, C.c_int, pp, cnt]
         L.m1o_implicit_cell.argtypes = [C.c_double] * 9 + [_dp]
         L.m1o_opacity.argtypes = [C.POINTER(Problem), C.c_double, C.c_double, _dp, _dp]
         L.m1o_opacity_many.argtypes = [C.POINTER(Problem), C.c_long, _dp, _dp, _dp, _dp]
@@ -168,13 +169,15 @@ class Oracle:
         return (_dp * len(arrs))(*[_ptr(a) for a in arrs])
 
     # -- steps --------------------------------------------------------------
-    def run(self, fields, dt, nsteps):
-        """Advance a copy of ``fields`` by nsteps; returns (fields, counters)."""
+    def run(self, fields, dt, nsteps, rk2=False):
+        """Advance a copy of ``fields`` by nsteps (Euler split steps, or RK2
+        with rk2=True); returns (fields, counters)."""
         st = {k: np.ascontiguousarray(v, dtype=np.float64).copy() for k, v in fields.items()}
         names = ("E", "Fx", "Fy", "Fz", "rho", "mx", "my", "mz", "Eg")
         arrs = self._arrs(st, names)
         cnt = (C.c_longlong * NCNT)()
-        rc = lib().m1o_run(C.byref(self.P), dt, int(nsteps), self._pp(arrs), cnt)
+        fn = lib().m1o_run_rk2 if rk2 else lib().m1o_run
+        rc = fn(C.byref(self.P), dt, int(nsteps), self._pp(arrs), cnt)
         if rc != 0:
             raise MemoryError("oracle run failed")
         return st, np.array(list(cnt))

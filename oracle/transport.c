@@ -300,3 +300,28 @@ int m1o_run(const m1o_problem *p, double dt, int nsteps, double *const st[9],
     free(buf);
     return 0;
 }
+
+/* Second-order Runge-Kutta stepping (Heun / SSP-RK2) with the split step as
+ * the stage operator, as the integration scheme of Sect. 2.4 applies the
+ * transport + source sequence to every sub-step:
+ *   U1 = S(T(U^n)),  U2 = S(T(U1)),  U^{n+1} = (U^n + U2) / 2
+ * for the radiation (E, F) and the gas (m, E_g); rho is frozen. */
+int m1o_run_rk2(const m1o_problem *p, double dt, int nsteps, double *const st[9],
+                long long cnt[M1O_NCNT])
+{
+    long N = (long)p->n[0] * p->n[1] * p->n[2];
+    double *save = malloc(9 * N * sizeof(double));
+    if (!save) return -1;
+    for (int s = 0; s < nsteps; ++s) {
+        for (int f = 0; f < 9; ++f) memcpy(save + f * N, st[f], N * sizeof(double));
+        if (m1o_run(p, dt, 2, st, cnt)) { free(save); return -1; }
+        for (int f = 0; f < 9; ++f) {
+            if (f == 4) continue;
+#pragma omp parallel for schedule(static)
+            for (long id = 0; id < N; ++id) st[f][id] = 0.5 * (save[f * N + id] + st[f][id]);
+        }
+    }
+    free(save);
+    return 0;
+}
+

@@ -330,4 +330,46 @@ hipError_t launch_opacity_eval(m1_ctx *c, long n, const double *rho, const doubl
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// RK2 averaging: U <- (U_saved + U) / 2 for E, F (form precision) and m, E_g
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_rk2_average(R *E, R *Fx, R *Fy, R *Fz, double *mx, double *my, double *mz,
+                                                     double *Eg, const unsigned char *save, long N, size_t per)
+{
+    const long id = blockIdx.x * 256L + threadIdx.x;
+    if (id >= N) return;
+    const R *sr[4] = {reinterpret_cast<const R *>(save), reinterpret_cast<const R *>(save + per),
+                      reinterpret_cast<const R *>(save + 2 * per), reinterpret_cast<const R *>(save + 3 * per)};
+    const double *sg = reinterpret_cast<const double *>(save + 4 * per);
+    E[id] = R(0.5) * (sr[0][id] + E[id]);
+    Fx[id] = R(0.5) * (sr[1][id] + Fx[id]);
+    Fy[id] = R(0.5) * (sr[2][id] + Fy[id]);
+    Fz[id] = R(0.5) * (sr[3][id] + Fz[id]);
+    mx[id] = 0.5 * (sg[id] + mx[id]);
+    my[id] = 0.5 * (sg[N + id] + my[id]);
+    mz[id] = 0.5 * (sg[2 * N + id] + mz[id]);
+    Eg[id] = 0.5 * (sg[3 * N + id] + Eg[id]);
+}
+
+hipError_t launch_rk2_average(m1_ctx *c)
+{
+    const long N = (long)c->n[0] * c->n[1] * c->n[2];
+    const size_t es = c->par.precision == M1_F32 ? 4 : 8;
+    const size_t per = ((N * es + 255) / 256) * 256;
+    dim3 block(256), grid((unsigned)((N + 255) / 256));
+    const unsigned char *sv = static_cast<const unsigned char *>(c->rk2_save);
+    if (c->par.precision == M1_F32)
+        hipLaunchKernelGGL((k_rk2_average<float>), grid, block, 0, c->stream, static_cast<float *>(c->f.E),
+                           static_cast<float *>(c->f.Fx), static_cast<float *>(c->f.Fy), static_cast<float *>(c->f.Fz),
+                           c->f.mx, c->f.my, c->f.mz, c->f.Eg, sv, N, per);
+    else
+        hipLaunchKernelGGL((k_rk2_average<double>), grid, block, 0, c->stream, static_cast<double *>(c->f.E),
+                           static_cast<double *>(c->f.Fx), static_cast<double *>(c->f.Fy),
+                           static_cast<double *>(c->f.Fz), c->f.mx, c->f.my, c->f.mz, c->f.Eg, sv, N, per);
+    return hipGetLastError();
+}
+
 } // namespace m1
+

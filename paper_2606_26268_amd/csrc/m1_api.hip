@@ -302,6 +302,7 @@ m1_status m1_destroy(m1_ctx *c)
     if (c->scratch) hipFree(c->scratch);
     if (c->table_dev) hipFree(c->table_dev);
     if (c->mlp_dev) hipFree(c->mlp_dev);
+    if (c->rk2_save) hipFree(c->rk2_save);
     delete c;
     return M1_OK;
 }
@@ -503,6 +504,42 @@ m1_status m1_step_implicit(m1_ctx *c, double dt)
     if (!(dt > 0) || !std::isfinite(dt)) return fail(M1_EINVAL, "m1_step_implicit: dt must be > 0");
     hipError_t e = launch_implicit(c, dt);
     if (e != hipSuccess) return hip_fail(e, "m1_step_implicit launch");
+    c->transported = false;
+    return M1_OK;
+}
+
+m1_status m1_step_rk2(m1_ctx *c, double dt)
+{
+    if (!c) return fail(M1_EINVAL, "m1_step_rk2: NULL context");
+    if (!c->bound) return fail(M1_ESTATE, "m1_step_rk2: no state bound");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(M1_EINVAL, "m1_step_rk2: dt must be > 0");
+    const long N = ncells(c);
+    const size_t per = ((N * elem_size(c) + 255) / 256) * 256;
+    if (!c->rk2_save) {
+        hipError_t e = hipMalloc(&c->rk2_save, 4 * per + 4 * N * sizeof(double));
+        if (e != hipSuccess) {
+            c->rk2_save = nullptr;
+            return fail(M1_ENOMEM, "m1_step_rk2: save buffer allocation failed");
+        }
+    }
+    unsigned char *sv = static_cast<unsigned char *>(c->rk2_save);
+    void *rad[4] = {c->f.E, c->f.Fx, c->f.Fy, c->f.Fz};
+    double *gas[4] = {c->f.mx, c->f.my, c->f.mz, c->f.Eg};
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < 4 && e == hipSuccess; ++v)
+        e = hipMemcpyAsync(sv + v * per, rad[v], N * elem_size(c), hipMemcpyDeviceToDevice, c->stream);
+    for (int v = 0; v < 4 && e == hipSuccess; ++v)
+        e = hipMemcpyAsync(sv + 4 * per + v * N * sizeof(double), gas[v], N * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "m1_step_rk2 save");
+    for (int stage = 0; stage < 2; ++stage) {
+        e = launch_transport(c, dt);
+        if (e == hipSuccess) e = launch_implicit(c, dt);
+        if (e != hipSuccess) return hip_fail(e, "m1_step_rk2 stage");
+    }
+    e = launch_rk2_average(c);
+    if (e == hipSuccess && c->op.kind != OPK_CONST) e = launch_opacity_init(c);
+    if (e != hipSuccess) return hip_fail(e, "m1_step_rk2 average");
     c->transported = false;
     return M1_OK;
 }

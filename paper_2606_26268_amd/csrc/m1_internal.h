@@ -74,6 +74,7 @@ struct m1_ctx {
     double *partials = nullptr;            // reduction scratch
     int npartial = 0;
     bool transported = false;
+    void *rk2_save = nullptr;              // state at t^n for m1_step_rk2
 
     // opacity
     m1::OpacityParams op{};
@@ -90,6 +91,7 @@ hipError_t launch_opacity_init(m1_ctx *c);
 hipError_t launch_opacity_eval(m1_ctx *c, long n, const double *rho, const double *T, double *kP,
                                double *kR);
 hipError_t launch_diag(m1_ctx *c, double out[8]);
+hipError_t launch_rk2_average(m1_ctx *c);
 int mlp_pack(m1_ctx *c, const float *theta, const double *norm);
 int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep);
 int mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, float *grad, double *loss);

@@ -413,28 +413,25 @@ __global__ void __launch_bounds__(256) k_mlp_eval(const float *pk, const float *
                                                   float *blockmax)
 {
     __shared__ float sh[2][256];
+    __shared__ MlpShared w;
+    mlp_stage(pk, w, threadIdx.x, blockDim.x);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
-    const long wave = (blockIdx.x * 256L + threadIdx.x) >> 6;
-    const long nwave = (gridDim.x * 256L) >> 6;
-    MlpWave net;
-    net.load(pk, lane);
+    const long id = blockIdx.x * 256L + threadIdx.x;
+    const long idc = id < n ? id : n - 1;
+    const float lr = samples[2 * idc], lt = samples[2 * idc + 1];
+    const float x0 = 2.0f * (lr - float(op.lr0)) / float(op.lr1 - op.lr0) - 1.0f;
+    const float x1 = 2.0f * (lt - float(op.lt0)) / float(op.lt1 - op.lt0) - 1.0f;
+    float y0, y1;
+    mlp_forward_shared(pk, w, x0, x1, lane, y0, y1);
+    double tP, tR;
+    table_lookup<double>(op, double(lr), double(lt), tP, tR);
+    const double dP = double(y0 * pk[MLP_OFF_NORM + 1] + pk[MLP_OFF_NORM + 0]) - tP;
+    const double dR = double(y1 * pk[MLP_OFF_NORM + 3] + pk[MLP_OFF_NORM + 2]) - tR;
     float mP = 0.f, mR = 0.f;
-    for (long base = wave * 64; base < n; base += nwave * 64) {
-        const long id = base + lane;
-        const long idc = id < n ? id : n - 1;
-        const float lr = samples[2 * idc], lt = samples[2 * idc + 1];
-        const float x0 = 2.0f * (lr - float(op.lr0)) / float(op.lr1 - op.lr0) - 1.0f;
-        const float x1 = 2.0f * (lt - float(op.lt0)) / float(op.lt1 - op.lt0) - 1.0f;
-        float y0, y1;
-        net.forward(x0, x1, lane, y0, y1);
-        double tP, tR;
-        table_lookup<double>(op, double(lr), double(lt), tP, tR);
-        const double dP = double(y0 * pk[MLP_OFF_NORM + 1] + pk[MLP_OFF_NORM + 0]) - tP;
-        const double dR = double(y1 * pk[MLP_OFF_NORM + 3] + pk[MLP_OFF_NORM + 2]) - tR;
-        if (id < n) {
-            mP = fmaxf(mP, float(fabs(exp10(dP) - 1.0)));
-            mR = fmaxf(mR, float(fabs(exp10(dR) - 1.0)));
-        }
+    if (id < n) {
+        mP = float(fabs(exp10(dP) - 1.0));
+        mR = float(fabs(exp10(dR) - 1.0));
     }
     sh[0][threadIdx.x] = mP;
     sh[1][threadIdx.x] = mR;
@@ -519,7 +516,7 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
     if (rc) return int(M1_EDEVICE);
 
     const int nblk = cfg->batch / 64;
-    const long n_eval_blocks = std::min<long>(1024, (cfg->n_eval + 255) / 256);
+    const long n_eval_blocks = (cfg->n_eval + 255) / 256;
     float *buf = nullptr;
     const size_t nbuf = 3 * size_t(NP) + size_t(nblk) * NP + nblk + cfg->steps + 2 * n_eval_blocks;
     if (hipMalloc(&buf, nbuf * sizeof(float)) != hipSuccess) {

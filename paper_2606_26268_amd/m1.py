@@ -73,7 +73,7 @@ class m1_train_report(C.Structure):
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = ("m1_params_default", "m1_create", "m1_destroy", "m1_set_stream", "m1_bind_state",
            "m1_set_opacity_model", "m1_set_opacity_table", "m1_set_opacity_mlp", "m1_mlp_train",
-           "m1_mlp_get", "m1_mlp_gradient", "m1_opacity_eval", "m1_max_dt", "m1_step_explicit", "m1_step_implicit",
+           "m1_mlp_get", "m1_mlp_gradient", "m1_opacity_eval", "m1_max_dt", "m1_step_explicit", "m1_step_implicit", "m1_step_rk2",
            "m1_transported", "m1_refresh_opacity", "m1_sync", "m1_diagnostics", "m1_last_error")
 
 _lib = None
@@ -103,6 +103,7 @@ def lib():
             "m1_max_dt": [vp, C.c_double, dp],
             "m1_step_explicit": [vp, C.c_double],
             "m1_step_implicit": [vp, C.c_double],
+            "m1_step_rk2": [vp, C.c_double],
             "m1_transported": [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)],
             "m1_refresh_opacity": [vp],
             "m1_sync": [vp],
@@ -247,6 +248,10 @@ def m1_step_implicit(ctx, dt):
     _check(lib().m1_step_implicit(ctx, float(dt)))
 
 
+def m1_step_rk2(ctx, dt):
+    _check(lib().m1_step_rk2(ctx, float(dt)))
+
+
 def m1_transported(ctx):
     ptrs = [C.c_void_p() for _ in range(4)]
     _check(lib().m1_transported(ctx, *[C.byref(p) for p in ptrs]))
@@ -326,10 +331,13 @@ class Solver:
         except Exception:
             pass
 
-    def step(self, dt, n=1):
+    def step(self, dt, n=1, rk2=False):
         for _ in range(n):
-            m1_step_explicit(self.ctx, dt)
-            m1_step_implicit(self.ctx, dt)
+            if rk2:
+                m1_step_rk2(self.ctx, dt)
+            else:
+                m1_step_explicit(self.ctx, dt)
+                m1_step_implicit(self.ctx, dt)
 
     def sync(self):
         m1_sync(self.ctx)

@@ -219,3 +219,33 @@ def test_error_paths():
         m1.m1_bind_state(s.ctx, bad)
     assert e.value.status == m1.M1_EINVAL
     s.close()
+
+
+def test_free_streaming_beam_2d(orc):
+    """The Sect. 3.2 oblique beam (f = 1 inside the beam, E ratio 1e8) on a
+    reduced 100x100 grid, 60 steps, FP64.  Near f = 1 the signal speeds are
+    square-root sensitive to rounding of f, so the tolerance is looser."""
+    p = I.make_beam(N=100, steps=60)
+    ref, cnt = run_oracle(orc, p, p.steps)
+    got, diag = run_gpu(p, "p64", p.steps)
+    assert_close(got, ref, dict(l1=1e-9, linf=1e-7), fields=RAD, label="beam p64")
+    assert diag["counters"][:3] == list(cnt[:3])
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_rk2_steps(orc, precision):
+    """m1_step_rk2 vs the oracle's RK2 on a spherical grid with the table."""
+    op = I.make_table()
+    p = _problem(I.SPHERICAL, (24, 12, 22), 3, seed=41, opacity=op)
+    o = orc.Oracle(p)
+    dt = o.max_dt(0.4)
+    ref, cnt = o.run(p.fields, dt, 8, rk2=True)
+    from paper_2606_26268_amd import m1
+    s = m1.Solver(p, precision)
+    s.step(dt, 8, rk2=True)
+    got = s.state()
+    s.close()
+    if precision == "p64":
+        assert_close(got, ref, TOL_P64, label="rk2 p64")
+    else:
+        assert_close_f32(got, ref, label="rk2 f32")
