@@ -56,6 +56,9 @@ typedef enum { M1_CARTESIAN = 0, M1_CYLINDRICAL = 1, M1_SPHERICAL = 2 } m1_geome
 typedef enum { M1_BC_PERIODIC = 0, M1_BC_OUTFLOW = 1 } m1_bc;
 typedef enum { M1_P64 = 0, M1_F32 = 1 } m1_precision;
 typedef enum { M1_OPAC_CONSTANT = 0, M1_OPAC_POWERLAW = 1 } m1_opacity_model;
+/* face treatment after reconstruction (Sect. 2.5; compared in Sect. 3.2) */
+typedef enum { M1_RECON_FPRESERVE = 0, M1_RECON_PLUTO = 1, M1_RECON_CLIP = 2 } m1_recon;
+typedef enum { M1_RIEMANN_HLL = 0, M1_RIEMANN_LF = 1 } m1_riemann;
 
 /* Grid: ndim active directions (1..3); n[d] interior cells (n[d] = 1 for an
  * inactive direction); faces[d] = n[d]+1 strictly increasing coordinates
@@ -75,13 +78,20 @@ typedef struct {
  * gamma   adiabatic index; C_v = rho / (gamma - 1) per volume (default 5/3)
  * precision  M1_P64 (all FP64) or M1_F32 (FP32 radiation storage and
  *         transport, FP64 implicit solve and gas)
- * e_floor lower bound enforced on E after transport (default 1e-30) */
+ * e_floor lower bound enforced on E after transport (default 1e-30)
+ * recon   face treatment: M1_RECON_FPRESERVE (default, Eq. f_reconstruct),
+ *         M1_RECON_PLUTO (flat face state whenever |R(F)| > R(E)) or
+ *         M1_RECON_CLIP (F_f = R(F) R(E)/|R(F)| whenever |R(F)| > R(E))
+ * riemann M1_RIEMANN_HLL (default) or M1_RIEMANN_LF (Lax-Friedrichs-Rusanov
+ *         with the largest limited signal speed) */
 typedef struct {
     double c;
     double a_rad;
     double gamma;
     int precision;
     double e_floor;
+    int recon;
+    int riemann;
 } m1_params;
 
 /* Caller-owned device state bound to a context (see conventions). */

@@ -126,3 +126,46 @@ int m1o_ffix(double *Ef, double Ff[3], double Ec, const double Fc[3])
     for (int a = 0; a < 3; ++a) Ff[a] = Fc[a];
     return 2;
 }
+
+/* Face treatments compared in the paper (Sect. 2.5 and the beam test of
+ * Sect. 3.2).  PLUTO: flat state (E_c, F_c) whenever |R(F)| > R(E).  Clip:
+ * F_f = R(F) R(E) / |R(F)| whenever |R(F)| > R(E).  Both keep the face state
+ * otherwise; a face energy <= 0 falls back to the flat state.  The default
+ * is the f-preserving fix (m1o_ffix).  Returns 0 = kept, 1 = changed,
+ * 2 = flat. */
+int m1o_face_fix(int recon, double *Ef, double Ff[3], double Ec, const double Fc[3])
+{
+    if (recon == M1O_RECON_FPRESERVE) return m1o_ffix(Ef, Ff, Ec, Fc);
+    double Fn = sqrt(Ff[0] * Ff[0] + Ff[1] * Ff[1] + Ff[2] * Ff[2]);
+    if (*Ef > 0.0 && Fn <= *Ef) return 0;
+    if (recon == M1O_RECON_CLIP && *Ef > 0.0) {
+        for (int a = 0; a < 3; ++a) Ff[a] = Ff[a] * (*Ef / Fn);
+        return 1;
+    }
+    *Ef = Ec;
+    for (int a = 0; a < 3; ++a) Ff[a] = Fc[a];
+    return 2;
+}
+
+/* Lax-Friedrichs-Rusanov flux (Sect. 2.5): the average flux minus the jump
+ * times the largest signal speed magnitude a = max(|lambda_L|, |lambda_R|),
+ * with the speeds of m1o_hll (including the optical-depth limiter). */
+void m1o_lf(const double UL[4], const double UR[4], int d, double tau, double c_hat, double out[4])
+{
+    double lmL, lpL, lmR, lpR, phiL[4], phiR[4];
+    m1o_speeds(UL[0], UL[1], UL[2], UL[3], d, &lmL, &lpL);
+    m1o_speeds(UR[0], UR[1], UR[2], UR[3], d, &lmR, &lpR);
+    m1o_flux(UL[0], UL[1], UL[2], UL[3], d, phiL);
+    m1o_flux(UR[0], UR[1], UR[2], UR[3], d, phiR);
+    double lamL = lmL < lmR ? lmL : lmR;
+    double lamR = lpL > lpR ? lpL : lpR;
+    if (tau > 0.0) {
+        double lim = 4.0 / (3.0 * tau);
+        if (lamL < -lim) lamL = -lim;
+        if (lamR > lim) lamR = lim;
+    }
+    double a = fabs(lamL) > fabs(lamR) ? fabs(lamL) : fabs(lamR);
+    for (int q = 0; q < 4; ++q)
+        out[q] = c_hat * (0.5 * (phiL[q] + phiR[q]) - 0.5 * a * (UR[q] - UL[q]));
+}
+

@@ -25,6 +25,9 @@ extern "C" {
 enum { M1O_CARTESIAN = 0, M1O_CYLINDRICAL = 1, M1O_SPHERICAL = 2 };
 enum { M1O_PERIODIC = 0, M1O_OUTFLOW = 1 };
 enum { M1O_CONST = 0, M1O_POWERLAW = 1, M1O_TABLE = 2, M1O_MLP = 3 };
+/* face treatment after reconstruction (Sect. 2.5, 3.2) and Riemann solver */
+enum { M1O_RECON_FPRESERVE = 0, M1O_RECON_PLUTO = 1, M1O_RECON_CLIP = 2 };
+enum { M1O_HLL = 0, M1O_LF = 1 };
 
 /* counters returned by the step routines */
 enum { M1O_CNT_EFLOOR = 0, M1O_CNT_FFIX_TRANSPORT = 1, M1O_CNT_FFIX_IMPLICIT = 2,
@@ -45,6 +48,8 @@ typedef struct {
     const double *mlp_theta;  /* flat parameters, order W1 b1 W2 b2 W3 b3 Ws */
     double mlp_norm[4];       /* mean_P, std_P, mean_R, std_R of log10 kappa */
     int mlp_bf16;             /* 1: round layer-2 operands like the GPU */
+    int recon;                /* M1O_RECON_* */
+    int riemann;              /* M1O_HLL or M1O_LF */
 } m1o_problem;
 
 /* --- closure, speeds, fluxes (Sect. 2.1, 2.5, 2.6) ------------------------ */
@@ -56,6 +61,8 @@ void m1o_hll(const double UL[4], const double UR[4], int d, double tau, double c
              double out[4], double *SL, double *SR);
 double m1o_vanleer(double dl, double dr);
 int m1o_ffix(double *Ef, double Ff[3], double Ec, const double Fc[3]);
+int m1o_face_fix(int recon, double *Ef, double Ff[3], double Ec, const double Fc[3]);
+void m1o_lf(const double UL[4], const double UR[4], int d, double tau, double c_hat, double out[4]);
 
 /* --- grid ----------------------------------------------------------------- */
 void m1o_cell_geometry(const m1o_problem *p, int i, int j, int k, double out[12]);

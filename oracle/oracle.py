@@ -55,6 +55,8 @@ class Problem(C.Structure):
         ("mlp_theta", C.POINTER(C.c_double)),
         ("mlp_norm", C.c_double * 4),
         ("mlp_bf16", C.c_int),
+        ("recon", C.c_int),
+        ("riemann", C.c_int),
     ]
 
 
@@ -77,6 +79,9 @@ def lib():
         L.m1o_vanleer.argtypes = [C.c_double, C.c_double]
         L.m1o_ffix.restype = C.c_int
         L.m1o_ffix.argtypes = [_dp, _dp, C.c_double, _dp]
+        L.m1o_face_fix.restype = C.c_int
+        L.m1o_face_fix.argtypes = [C.c_int, _dp, _dp, C.c_double, _dp]
+        L.m1o_lf.argtypes = [_dp, _dp, C.c_int, C.c_double, C.c_double, _dp]
         L.m1o_cell_geometry.argtypes = [C.POINTER(Problem), C.c_int, C.c_int, C.c_int, _dp]
         L.m1o_max_dt.restype = C.c_double
         L.m1o_max_dt.argtypes = [C.POINTER(Problem), C.c_double]
@@ -126,6 +131,8 @@ class Oracle:
             P.bc[d][0], P.bc[d][1] = prob.bc[d]
         P.c_hat, P.c, P.a_rad = prob.c_hat, prob.c, prob.a_rad
         P.gamma, P.e_floor = prob.gamma, prob.e_floor
+        P.recon = getattr(prob, "recon", 0)
+        P.riemann = getattr(prob, "riemann", 0)
         op = prob.opacity
         P.opac_kind = op["kind"]
         P.sigma = op.get("sigma", 0.0)
@@ -272,6 +279,22 @@ def ffix(Ef, Ff, Ec, Fc):
     Fc = np.ascontiguousarray(Fc, dtype=np.float64)
     br = lib().m1o_ffix(C.byref(e), _ptr(Ff), float(Ec), _ptr(Fc))
     return br, e.value, Ff
+
+
+def face_fix(recon, Ef, Ff, Ec, Fc):
+    e = C.c_double(Ef)
+    Ff = np.ascontiguousarray(Ff, dtype=np.float64).copy()
+    Fc = np.ascontiguousarray(Fc, dtype=np.float64)
+    br = lib().m1o_face_fix(int(recon), C.byref(e), _ptr(Ff), float(Ec), _ptr(Fc))
+    return br, e.value, Ff
+
+
+def lf(UL, UR, d, tau=0.0, c_hat=1.0):
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    out = np.zeros(4)
+    lib().m1o_lf(_ptr(UL), _ptr(UR), int(d), float(tau), float(c_hat), _ptr(out))
+    return out
 
 
 def implicit_cell(Es, Cv, T, kP, rho, dt, c_hat, c, a=1.0):

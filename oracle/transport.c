@@ -127,7 +127,8 @@ static long lin(const m1o_problem *p, const int c[3])
 
 /* Piecewise-linear van Leer reconstruction of (E, Fx, Fy, Fz) of cell t
  * along d, evaluated on its upper face (side = +1) or lower face (side = -1),
- * followed by the f-preserving fix against that cell's centre values.
+ * followed by the face treatment (f-preserving fix by default) against that
+ * cell's centre values.
  * The slope uses divided differences over centre spacings. */
 static void face_state(const m1o_problem *p, const double *const st[9], int d, int cbase[3],
                        int t, int side, double U[4])
@@ -149,7 +150,7 @@ static void face_state(const m1o_problem *p, const double *const st[9], int d, i
     }
     double Fc[3] = {q[1][1], q[1][2], q[1][3]};
     double Ff[3] = {U[1], U[2], U[3]};
-    m1o_ffix(&U[0], Ff, q[1][0], Fc);
+    m1o_face_fix(p->recon, &U[0], Ff, q[1][0], Fc);
     U[1] = Ff[0]; U[2] = Ff[1]; U[3] = Ff[2];
 }
 
@@ -215,7 +216,10 @@ int m1o_explicit(const m1o_problem *p, double dt, const double *const st[9],
             ca[d] = src_index(p, d, f - 1);
             cb[d] = src_index(p, d, f);
             double tface = 0.5 * (tau[lin(p, ca)] + tau[lin(p, cb)]);
-            m1o_hll(UL, UR, d, tface, p->c_hat, out4, NULL, NULL);
+            if (p->riemann == M1O_LF)
+                m1o_lf(UL, UR, d, tface, p->c_hat, out4);
+            else
+                m1o_hll(UL, UR, d, tface, p->c_hat, out4, NULL, NULL);
             for (int q = 0; q < 4; ++q) flux[d][fid * 4 + q] = out4[q];
         }
     }

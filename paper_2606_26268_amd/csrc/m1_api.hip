@@ -233,6 +233,8 @@ m1_status m1_params_default(double c_hat, m1_params *p)
     p->gamma = 5.0 / 3.0;
     p->precision = M1_P64;
     p->e_floor = 1e-30;
+    p->recon = M1_RECON_FPRESERVE;
+    p->riemann = M1_RIEMANN_HLL;
     return M1_OK;
 }
 
@@ -268,6 +270,9 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
     if (p) par = *p;
     if (par.precision != M1_P64 && par.precision != M1_F32)
         return fail(M1_EINVAL, "m1_create: unknown precision");
+    if (par.recon < M1_RECON_FPRESERVE || par.recon > M1_RECON_CLIP || par.riemann < M1_RIEMANN_HLL ||
+        par.riemann > M1_RIEMANN_LF)
+        return fail(M1_EINVAL, "m1_create: unknown reconstruction or Riemann solver");
     if (!(par.c > 0.0) || !(par.gamma > 1.0) || !(par.a_rad > 0.0))
         return fail(M1_EINVAL, "m1_create: c, a_rad must be > 0 and gamma > 1");
     m1_ctx *c = new (std::nothrow) m1_ctx();

@@ -6,6 +6,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/m1.h"
+
 namespace m1 {
 
 // Arithmetic primitives per precision.  FP64: IEEE square root; reciprocal
@@ -74,7 +76,8 @@ __device__ __forceinline__ Wave<R> closure_wave(R E, R Fx, R Fy, R Fz)
 // -+4/(3 tau) for tau > 0 (Sect. 2.6), S_L = min(lambda_L, 0),
 // S_R = max(lambda_R, 0); S_L = S_R = 0 falls back to the average flux.
 template <typename R, int D>
-__device__ __forceinline__ void hll_flux(const R UL[4], const R UR[4], R tau, R c_hat, R out[4])
+__device__ __forceinline__ void hll_flux(const R UL[4], const R UR[4], R tau, R c_hat, R out[4],
+                                         int riemann = M1_RIEMANN_HLL)
 {
     const Wave<R> wl = closure_wave<R, D>(UL[0], UL[1], UL[2], UL[3]);
     const Wave<R> wr = closure_wave<R, D>(UR[0], UR[1], UR[2], UR[3]);
@@ -84,6 +87,13 @@ __device__ __forceinline__ void hll_flux(const R UL[4], const R UR[4], R tau, R 
         const R lim = R(4) / (R(3) * tau);
         lamL = lamL < -lim ? -lim : lamL;
         lamR = lamR > lim ? lim : lamR;
+    }
+    if (riemann == M1_RIEMANN_LF) {
+        const R aL = lamL < R(0) ? -lamL : lamL, aR = lamR < R(0) ? -lamR : lamR;
+        const R sp = aL > aR ? aL : aR;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = c_hat * (R(0.5) * (wl.phi[q] + wr.phi[q]) - R(0.5) * sp * (UR[q] - UL[q]));
+        return;
     }
     const R SL = lamL < R(0) ? lamL : R(0);
     const R SR = lamR > R(0) ? lamR : R(0);
@@ -190,6 +200,30 @@ __device__ __forceinline__ void ffix_sq(R U[4], const R C[4])
     }
 }
 
+// Face treatment selected at run time: the f-preserving fix (default), the
+// "PLUTO" flat fallback or the simple clip (the alternatives of Sect. 2.5 and
+// the beam comparison of Sect. 3.2); both alternatives act only when
+// |R(F)| > R(E) and fall back to the flat state for R(E) <= 0.
+template <typename R>
+__device__ __forceinline__ void face_fix(int recon, R U[4], const R C[4])
+{
+    if (recon == M1_RECON_FPRESERVE) {
+        ffix_sq(U, C);
+        return;
+    }
+    const R Ff2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    if (U[0] > R(0) && Ff2 <= U[0] * U[0]) return;
+    if (recon == M1_RECON_CLIP && U[0] > R(0)) {
+        const R sc = U[0] * Num<R>::rcp(Num<R>::sqrt_(Ff2));
+        U[1] *= sc;
+        U[2] *= sc;
+        U[3] *= sc;
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) U[q] = C[q];
+}
+
 template <typename R>
 __device__ __forceinline__ R vanleer_fast(R dl, R dr)
 {
@@ -203,7 +237,8 @@ __device__ __forceinline__ R vanleer_fast(R dl, R dr)
 // f-preserving fix, both closures, the optical-depth-limited HLL speeds.
 template <typename R>
 __device__ __forceinline__ void face_flux(int d, const R qa[4], const R qb[4], const R qc[4], const R qd[4],
-                                          R wA, R wB, R wC, R hpL, R hmR, R tauL, R tauR, R c_hat, R out[4])
+                                          R wA, R wB, R wC, R hpL, R hmR, R tauL, R tauR, R c_hat, R out[4],
+                                          int recon = M1_RECON_FPRESERVE, int riemann = M1_RIEMANN_HLL)
 {
     R UL[4], UR[4];
 #pragma unroll
@@ -214,8 +249,8 @@ __device__ __forceinline__ void face_flux(int d, const R qa[4], const R qb[4], c
         UL[v] = qb[v] + vanleer_fast(dAB, dBC) * hpL;
         UR[v] = qc[v] - vanleer_fast(dBC, dCD) * hmR;
     }
-    ffix_sq(UL, qb);
-    ffix_sq(UR, qc);
+    face_fix(recon, UL, qb);
+    face_fix(recon, UR, qc);
     const Wave<R> wl = closure_wave_rt(UL[0], UL[1], UL[2], UL[3], d);
     const Wave<R> wr = closure_wave_rt(UR[0], UR[1], UR[2], UR[3], d);
     R lamL = wl.lm < wr.lm ? wl.lm : wr.lm;
@@ -225,6 +260,14 @@ __device__ __forceinline__ void face_flux(int d, const R qa[4], const R qb[4], c
         const R lim = R(4) / R(3) * Num<R>::rcp(tau);
         lamL = lamL < -lim ? -lim : lamL;
         lamR = lamR > lim ? lim : lamR;
+    }
+    if (riemann == M1_RIEMANN_LF) {
+        // Lax-Friedrichs-Rusanov: largest limited speed magnitude
+        const R aL = lamL < R(0) ? -lamL : lamL, aR = lamR < R(0) ? -lamR : lamR;
+        const R sp = aL > aR ? aL : aR;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = c_hat * (R(0.5) * (wl.phi[q] + wr.phi[q]) - R(0.5) * sp * (UR[q] - UL[q]));
+        return;
     }
     const R SL = lamL < R(0) ? lamL : R(0);
     const R SR = lamR > R(0) ? lamR : R(0);

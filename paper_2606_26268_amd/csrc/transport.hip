@@ -21,6 +21,7 @@ struct TArgs {
     int ign[3];
     Metric<R> m;
     R dt, c_hat, e_floor;
+    int recon, riemann;
     unsigned long long *cnt;
 };
 
@@ -78,14 +79,21 @@ __device__ __forceinline__ void direction_div(const TArgs<R> &a, int base, int s
         Lt[v] = q[2][v] + s0 * hp[t + 2];
         Rp[v] = q[3][v] - sp * hm[t + 3];
     }
-    ffix(Lm, q[1]);
-    ffix(Rt, q[2]);
-    ffix(Lt, q[2]);
-    ffix(Rp, q[3]);
+    if (a.recon == M1_RECON_FPRESERVE) {
+        ffix(Lm, q[1]);
+        ffix(Rt, q[2]);
+        ffix(Lt, q[2]);
+        ffix(Rp, q[3]);
+    } else {
+        face_fix(a.recon, Lm, q[1]);
+        face_fix(a.recon, Rt, q[2]);
+        face_fix(a.recon, Lt, q[2]);
+        face_fix(a.recon, Rp, q[3]);
+    }
     const R tm = a.tau[li[1]], t0 = a.tau[li[2]], tp = a.tau[li[3]];
     R flo[4], fhi[4];
-    hll_flux<R, D>(Lm, Rt, R(0.5) * (tm + t0), a.c_hat, flo);
-    hll_flux<R, D>(Lt, Rp, R(0.5) * (t0 + tp), a.c_hat, fhi);
+    hll_flux<R, D>(Lm, Rt, R(0.5) * (tm + t0), a.c_hat, flo, a.riemann);
+    hll_flux<R, D>(Lt, Rp, R(0.5) * (t0 + tp), a.c_hat, fhi, a.riemann);
     const R al = a.m.alo[D][t] * tr, ah = a.m.ahi[D][t] * tr;
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] += ah * fhi[v] - al * flo[v];
@@ -194,9 +202,12 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
 constexpr int TX = 32, TY = 8, HX = TX + 4, HY = TY + 4, NT = TX * TY;
 constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX, NHALO = 2 * (2 * TY + 2 * TX);
 
-template <typename R, int GEOM>
+template <typename R, int GEOM, bool VARIANTS>
 __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
 {
+    // the default scheme (f-preserving fix + HLL) is a compile-time constant
+    const int recon = VARIANTS ? a.recon : int(M1_RECON_FPRESERVE);
+    const int riemann = VARIANTS ? a.riemann : int(M1_RIEMANN_HLL);
     __shared__ R sq[4][HY][HX];
     __shared__ R st[HY][HX];
     __shared__ R sfx[4][TY][TX + 1];
@@ -247,7 +258,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         T1 = a.tau[zlin(z0, col)];
         T2 = a.tau[zlin(z0 + 1, col)];
         face_flux<R>(2, Q0, W[0], W[1], W[2], wz[z0 + 1], wz[z0 + 2], wz[z0 + 3], hpz[z0 + 1], hmz[z0 + 2],
-                     Tm, T1, a.c_hat, Fzlo);
+                     Tm, T1, a.c_hat, Fzlo, recon, riemann);
     }
 
     for (int k = z0; k < z1; ++k) {
@@ -294,7 +305,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
             const R *wv = a.m.winv[d], *hpv = a.m.hp[d], *hmv = a.m.hm[d];
             R fl[4];
             face_flux<R>(d, qs[0], qs[1], qs[2], qs[3], wv[gidx + 1], wv[gidx + 2], wv[gidx + 3], hpv[gidx + 1],
-                         hmv[gidx + 2], tl, tr, a.c_hat, fl);
+                         hmv[gidx + 2], tl, tr, a.c_hat, fl, recon, riemann);
             if (d == 0) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) sfx[v][r0 - 2][c0] = fl[v];
@@ -305,7 +316,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         }
         // z face above the plane from the register window
         face_flux<R>(2, W[0], W[1], W[2], W[3], wz[k + 2], wz[k + 3], wz[k + 4], hpz[k + 2], hmz[k + 3], T1, T2,
-                     a.c_hat, Fzhi);
+                     a.c_hat, Fzhi, recon, riemann);
         __syncthreads();
 
         if (live) {
@@ -354,6 +365,8 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
     a.dt = R(dt);
     a.c_hat = R(c->c_hat);
     a.e_floor = R(c->par.e_floor);
+    a.recon = c->par.recon;
+    a.riemann = c->par.riemann;
     a.cnt = c->cnt;
     const int N = c->n[0] * c->n[1] * c->n[2];
     if (c->ndim == 3) {
@@ -363,20 +376,22 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
         while (nz > 4 && (long)tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz) < 2048) nz /= 2;
         const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
         const int launched = ((nblocks + 7) / 8) * 8;
+        const bool var = c->par.recon != M1_RECON_FPRESERVE || c->par.riemann != M1_RIEMANN_HLL;
+#define M1_T3D(G, V)                                                                                  \
+    hipLaunchKernelGGL((k_transport3d<R, G, V>), dim3(launched), dim3(NT), 0, c->stream, a, nz, tiles_x, \
+                       tiles_y, nblocks)
         switch (c->geom) {
         case M1_CARTESIAN:
-            hipLaunchKernelGGL((k_transport3d<R, M1_CARTESIAN>), dim3(launched), dim3(NT), 0, c->stream, a, nz,
-                               tiles_x, tiles_y, nblocks);
+            if (var) M1_T3D(M1_CARTESIAN, true); else M1_T3D(M1_CARTESIAN, false);
             break;
         case M1_CYLINDRICAL:
-            hipLaunchKernelGGL((k_transport3d<R, M1_CYLINDRICAL>), dim3(launched), dim3(NT), 0, c->stream, a, nz,
-                               tiles_x, tiles_y, nblocks);
+            if (var) M1_T3D(M1_CYLINDRICAL, true); else M1_T3D(M1_CYLINDRICAL, false);
             break;
         default:
-            hipLaunchKernelGGL((k_transport3d<R, M1_SPHERICAL>), dim3(launched), dim3(NT), 0, c->stream, a, nz,
-                               tiles_x, tiles_y, nblocks);
+            if (var) M1_T3D(M1_SPHERICAL, true); else M1_T3D(M1_SPHERICAL, false);
             break;
         }
+#undef M1_T3D
         return hipGetLastError();
     }
     dim3 block(256), grid((N + 255) / 256);

@@ -53,6 +53,8 @@ class Problem:
     fields: dict = field(default_factory=dict)
     dt: float = 0.0
     steps: int = 1
+    recon: int = 0      # 0 f-preserving, 1 PLUTO flat, 2 simple clip
+    riemann: int = 0    # 0 HLL, 1 Lax-Friedrichs-Rusanov
 
     @property
     def shape(self):

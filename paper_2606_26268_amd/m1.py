@@ -24,6 +24,8 @@ M1_CARTESIAN, M1_CYLINDRICAL, M1_SPHERICAL = 0, 1, 2
 M1_BC_PERIODIC, M1_BC_OUTFLOW = 0, 1
 M1_P64, M1_F32 = 0, 1
 M1_OPAC_CONSTANT, M1_OPAC_POWERLAW = 0, 1
+M1_RECON_FPRESERVE, M1_RECON_PLUTO, M1_RECON_CLIP = 0, 1, 2
+M1_RIEMANN_HLL, M1_RIEMANN_LF = 0, 1
 M1_MLP_NPARAM = 4486
 
 
@@ -40,7 +42,7 @@ class m1_grid(C.Structure):
 
 class m1_params(C.Structure):
     _fields_ = [("c", C.c_double), ("a_rad", C.c_double), ("gamma", C.c_double),
-                ("precision", C.c_int), ("e_floor", C.c_double)]
+                ("precision", C.c_int), ("e_floor", C.c_double), ("recon", C.c_int), ("riemann", C.c_int)]
 
 
 class m1_fields(C.Structure):
@@ -301,6 +303,7 @@ class Solver:
         par = m1_params_default(prob.c_hat)
         par.c, par.a_rad, par.gamma = prob.c, prob.a_rad, prob.gamma
         par.precision, par.e_floor = self.precision, prob.e_floor
+        par.recon, par.riemann = getattr(prob, "recon", 0), getattr(prob, "riemann", 0)
         self.ctx = m1_create(prob.ndim, prob.n, prob.faces, prob.bc, prob.geometry, prob.c_hat, par)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         m1_set_stream(self.ctx, self.stream.cuda_stream)

@@ -249,3 +249,17 @@ def test_rk2_steps(orc, precision):
         assert_close(got, ref, TOL_P64, label="rk2 p64")
     else:
         assert_close_f32(got, ref, label="rk2 f32")
+
+
+@pytest.mark.parametrize("recon,riemann", [(1, 0), (2, 0), (0, 1)])
+def test_face_treatment_and_riemann_variants(orc, recon, riemann):
+    """PLUTO / clip face treatments and the Lax-Friedrichs flux, 3D and 2D."""
+    for geom, n, ndim in ((I.CARTESIAN, (33, 17, 9), 3), (I.SPHERICAL, (27, 14, 1), 2)):
+        p = _problem(geom, n, ndim, seed=51 + recon + 3 * riemann)
+        p.recon, p.riemann = recon, riemann
+        o = orc.Oracle(p)
+        dt = o.max_dt(0.4)
+        ref, cnt = o.run(p.fields, dt, 6)
+        got, diag = run_gpu(p, "p64", 6, dt=dt)
+        assert_close(got, ref, TOL_P64, label=f"recon {recon} riemann {riemann} ndim {ndim}")
+        assert diag["counters"][:3] == list(cnt[:3])

@@ -185,3 +185,33 @@ def test_ffix_branches(orc):
     # non-positive face energy: flat state
     br, E, F = orc.ffix(-1.0, [0.1, 0, 0], 2.0, [1.0, 0.2, 0])
     assert br == 2 and E == 2.0 and np.allclose(F, [1.0, 0.2, 0])
+
+
+def test_alternative_face_treatments(orc):
+    """PLUTO flat fallback and simple clip (Sect. 2.5 / 3.2) act only when
+    |R(F)| > R(E); clip restores f = 1 along R(F), PLUTO the cell state."""
+    for recon in (1, 2):
+        br, E, F = orc.face_fix(recon, 1.0, [0.6, 0.2, 0.0], 2.0, [1.0, 0.2, 0.0])
+        assert br == 0 and np.allclose(F, [0.6, 0.2, 0.0]) and E == 1.0
+    br, E, F = orc.face_fix(1, 1.0, [1.2, 0.5, 0.0], 2.0, [1.0, 0.2, 0.0])
+    assert br == 2 and E == 2.0 and np.allclose(F, [1.0, 0.2, 0.0])
+    br, E, F = orc.face_fix(2, 1.0, [1.2, 0.5, 0.0], 2.0, [1.0, 0.2, 0.0])
+    assert br == 1 and E == 1.0 and abs(np.linalg.norm(F) - 1.0) < 1e-15
+    assert abs(F[1] / F[0] - 0.5 / 1.2) < 1e-15
+
+
+def test_lax_friedrichs_flux(orc):
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        U = np.concatenate([[math.exp(rng.normal())], 0.5 * rng.uniform(-1, 1, 3)])
+        d = int(rng.integers(0, 3))
+        np.testing.assert_allclose(orc.lf(U, U, d, c_hat=3.0), 3.0 * orc.flux(U[0], U[1:], d), rtol=1e-14, atol=1e-14)
+    # symmetric speeds: LF and HLL coincide (both Rusanov)
+    UL, UR = np.array([2.0, 0, 0, 0]), np.array([1.0, 0, 0, 0])
+    np.testing.assert_allclose(orc.lf(UL, UR, 0), orc.hll(UL, UR, 0)[0], rtol=1e-15, atol=1e-15)
+    # one-sided speeds: LF adds dissipation HLL (upwind) does not
+    UL, UR = np.array([2.0, 2.0, 0, 0]), np.array([1.0, 1.0, 0, 0])
+    lf, hll = orc.lf(UL, UR, 0), orc.hll(UL, UR, 0)[0]
+    np.testing.assert_allclose(hll, [2.0, 2.0, 0, 0], rtol=1e-15)
+    np.testing.assert_allclose(lf, 0.5 * (orc.flux(2.0, [2, 0, 0], 0) + orc.flux(1.0, [1, 0, 0], 0)) - 0.5 * (UR - UL),
+                               rtol=1e-15)

@@ -425,3 +425,28 @@ def test_rk2_conserves_rescaled_totals(orc):
     e0 = (p.fields["Eg"] + r * p.fields["E"]).sum()
     e1 = (out["Eg"] + r * out["E"]).sum()
     assert abs(e1 - e0) <= 1e-13 * abs(e0)
+
+
+def test_beam_face_treatments(orc):
+    """Oblique beam (Sect. 3.2) at 200^2, t = 2.5: the packet moves at c_hat
+    with every face treatment; the f-preserving fix needs no cell-centre
+    f <= 1 fix-up while the simple clip needs many (the accumulation of
+    face/centre mismatches the paper blames for the exploding beam), and the
+    PLUTO flat fallback is the most diffusive (lowest peak)."""
+    res = {}
+    for recon in (0, 1, 2):
+        p = I.make_beam(N=200, steps=None)
+        p.recon = recon
+        out, cnt = orc.Oracle(p).run(p.fields, p.dt, int(2.5 / p.dt))
+        E = out["E"][0] - 1e4
+        c = (np.arange(200) + 0.5) * 5 / 200
+        Y, X = np.meshgrid(c, c, indexing="ij")
+        w = np.clip(E, 0, None)
+        s = ((X + Y) / math.sqrt(2) * w).sum() / w.sum()
+        res[recon] = (s, E.max(), cnt)
+    t = int(2.5 / I.make_beam(N=200).dt) * I.make_beam(N=200).dt
+    s0 = (0.55 + 0.37) / math.sqrt(2)
+    for recon, (s, pk, cnt) in res.items():
+        assert abs(s - s0 - t) < 0.05, (recon, s)
+    assert res[0][2][1] == 0 and res[2][2][1] > 1000
+    assert res[1][1] < 0.95 * res[0][1]
