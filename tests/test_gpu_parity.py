@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 from paper_2606_26268_amd import inputs as I
-from tests.gpu_common import ALL, RAD, TOL_P64, assert_close, assert_close_f32, run_gpu, run_oracle, say
+from tests.gpu_common import (ALL, RAD, TOL_P64, TOL_P64_F1, assert_close, assert_close_f32, run_gpu, run_oracle,
+                               say)
 
 pytestmark = pytest.mark.gpu
 
@@ -228,7 +229,7 @@ def test_free_streaming_beam_2d(orc):
     p = I.make_beam(N=100, steps=60)
     ref, cnt = run_oracle(orc, p, p.steps)
     got, diag = run_gpu(p, "p64", p.steps)
-    assert_close(got, ref, dict(l1=1e-9, linf=1e-7), fields=RAD, label="beam p64")
+    assert_close(got, ref, TOL_P64_F1, fields=RAD, label="beam p64")
     assert diag["counters"][:3] == list(cnt[:3])
 
 
@@ -261,5 +262,7 @@ def test_face_treatment_and_riemann_variants(orc, recon, riemann):
         dt = o.max_dt(0.4)
         ref, cnt = o.run(p.fields, dt, 6)
         got, diag = run_gpu(p, "p64", 6, dt=dt)
-        assert_close(got, ref, TOL_P64, label=f"recon {recon} riemann {riemann} ndim {ndim}")
+        # the clip sets faces to f = 1 exactly, where the speeds are sqrt-sensitive
+        tol = TOL_P64_F1 if recon == 2 else TOL_P64
+        assert_close(got, ref, tol, label=f"recon {recon} riemann {riemann} ndim {ndim}")
         assert diag["counters"][:3] == list(cnt[:3])
