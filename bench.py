@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--only", action="store_true", help="time the headline form only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--train-steps", type=int, default=30000)
+    ap.add_argument("--train-steps", type=int, default=None, help="override the Adam step count")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -58,8 +58,10 @@ def train_surrogate(m1, I, torch, solver, steps):
     import numpy as np
     smp = np.concatenate([I.mlp_samples(ntr, 4), I.mlp_samples(nev, 5)])
     dsmp = torch.from_numpy(smp).to("cuda")
-    rep = m1.m1_mlp_train(solver.ctx, dsmp, ntr, nev, I.mlp_init(7), batch=1024, steps=steps,
-                          lr=2e-3, lr_final=2e-6)
+    cfg = dict(I.MLP_TRAIN)
+    if steps:
+        cfg["steps"] = steps
+    rep = m1.m1_mlp_train(solver.ctx, dsmp, ntr, nev, I.mlp_init(7), **cfg)
     return rep
 
 

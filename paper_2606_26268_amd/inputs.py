@@ -251,6 +251,8 @@ MLP_IN, MLP_HID, MLP_OUT = 2, 64, 2
 MLP_LAYOUT = (("W1", (64, 2)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
               ("W3", (2, 64)), ("b3", (2,)), ("Ws", (2, 2)))
 MLP_NPARAM = sum(int(np.prod(s)) for _, s in MLP_LAYOUT)
+# training schedule used by the benchmark and the tests (Adam, cosine decay)
+MLP_TRAIN = dict(batch=4096, steps=600000, lr=7e-4, lr_final=7e-7)
 
 
 def mlp_unflatten(theta):
@@ -263,11 +265,14 @@ def mlp_unflatten(theta):
 
 
 def mlp_init(seed=7):
-    """Seeded Glorot-uniform weights, zero biases and shortcut (float32)."""
+    """Seeded Glorot-uniform hidden weights; zero biases, zero output layer and
+    zero shortcut (float32).  The trainer fits the shortcut to the table by
+    least squares, so the network starts at that plane and the tanh layers
+    learn only the residual."""
     rng = np.random.Generator(np.random.PCG64(seed))
     parts = []
     for name, shp in MLP_LAYOUT:
-        if name.startswith("W") and name != "Ws":
+        if name in ("W1", "W2"):
             fan_out, fan_in = shp
             lim = math.sqrt(6.0 / (fan_in + fan_out))
             parts.append(rng.uniform(-lim, lim, shp).ravel())

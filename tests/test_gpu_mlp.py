@@ -93,8 +93,7 @@ def trained():
     ntr, nev = 1_000_000, 100_000
     smp = np.concatenate([I.mlp_samples(ntr, 4), I.mlp_samples(nev, 5)])
     dsmp = torch.from_numpy(smp).to("cuda")
-    rep = m1.m1_mlp_train(s.ctx, dsmp, ntr, nev, I.mlp_init(7), batch=1024, steps=30000,
-                          lr=2e-3, lr_final=2e-6)
+    rep = m1.m1_mlp_train(s.ctx, dsmp, ntr, nev, I.mlp_init(7), **I.MLP_TRAIN)
     say(f"  training: {rep}")
     th, norm = m1.m1_mlp_get(s.ctx)
     return m1, s, tab, smp[ntr:], th, norm, rep

@@ -67,8 +67,9 @@ def test_bf16_rounding_matches_library(orc):
 
 
 def test_bf16_split_forward_close_to_exact(orc):
-    th = I.mlp_init(5).astype(np.float64)
-    x = np.random.default_rng(2).uniform(-1, 1, (500, 2))
+    rng = np.random.default_rng(2)
+    th = I.mlp_init(5).astype(np.float64) + 0.05 * rng.normal(size=I.MLP_NPARAM)
+    x = rng.uniform(-1, 1, (500, 2))
     y64 = orc.mlp_forward(th, x, bf16=False)
     y16 = orc.mlp_forward(th, x, bf16=True)
     # hi*hi + hi*lo + lo*hi keeps ~16 significant bits per product
