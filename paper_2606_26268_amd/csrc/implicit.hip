@@ -51,15 +51,25 @@ __device__ __forceinline__ double gas_T(double rho, double mx, double my, double
     return (Eg - 0.5 * (mx * mx + my * my + mz * mz) / rho) / Cv;
 }
 
-// One cell of the implicit step; returns the new gas temperature.
+// Gas temperature with the reciprocal density supplied:
+// T = (E_g - |m|^2 / (2 rho)) (gamma - 1) / rho.
+__device__ __forceinline__ double gas_T_r(double inv_rho, double mx, double my, double mz, double Eg,
+                                          double gm1)
+{
+    return (Eg - 0.5 * (mx * mx + my * my + mz * mz) * inv_rho) * (gm1 * inv_rho);
+}
+
+// One cell of the implicit step; returns the new gas temperature.  Four
+// FP64 divisions per cell: 1/rho, the determinant, the flux damping factor
+// and the optical depth per length.
 template <typename R, bool CONST_OPAC>
 __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i, int j, int k)
 {
     const double rho = a.rho[id];
     double mx = a.mx[id], my = a.my[id], mz = a.mz[id], Eg = a.Eg[id];
-    const double gam = a.k.gamma;
-    const double Cv = rho / (gam - 1.0);
-    const double T = gas_T(rho, mx, my, mz, Eg, gam);
+    const double inv_rho = 1.0 / rho;
+    const double Cv = rho * a.k.inv_gm1;
+    const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
     double rkP, rchi;
     if (CONST_OPAC) {
         rkP = rho * a.op.kP;
@@ -73,13 +83,13 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     // Eq. implicit_matrix with gamma_abs,red = dt c_hat kappa_P rho and
     // gamma_abs = dt c kappa_P rho, inverted by Cramer's rule in a
     // cancellation-free arrangement (det > 0)
-    const double gr = a.k.dt * a.k.c_hat * rkP;
-    const double g = a.k.dt * a.k.c * rkP;
+    const double gr = a.k.dt_ch * rkP;
+    const double g = a.k.dt_c * rkP;
     const double aT3 = a.k.a * T * T * T, aT4 = aT3 * T;
     const double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
     double E1 = (Cv * (Es + gr * aT4) + 4.0 * g * aT3 * Es) / det;
-    const double damp = 1.0 + a.k.dt * a.k.c_hat * rchi;   // Eq. source_discrete2
-    double F1[3] = {Fs[0] / damp, Fs[1] / damp, Fs[2] / damp};
+    const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rchi);   // Eq. source_discrete2
+    double F1[3] = {Fs[0] * inv_damp, Fs[1] * inv_damp, Fs[2] * inv_damp};
     const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
     if (Fn > E1) {
         const double s = E1 / Fn;
@@ -91,11 +101,10 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     // stored (possibly float) values define the exchanged amounts, so the
     // rescaled totals E_g + (c/c_hat) E and m + F/c_hat are conserved
     const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
-    const double inv_ch = 1.0 / a.k.c_hat;
-    Eg -= (a.k.c * inv_ch) * (double(E1r) - Es);
-    mx -= (double(F1r[0]) - Fs[0]) * inv_ch;
-    my -= (double(F1r[1]) - Fs[1]) * inv_ch;
-    mz -= (double(F1r[2]) - Fs[2]) * inv_ch;
+    Eg -= a.k.c_ratio * (double(E1r) - Es);
+    mx -= (double(F1r[0]) - Fs[0]) * a.k.inv_ch;
+    my -= (double(F1r[1]) - Fs[1]) * a.k.inv_ch;
+    mz -= (double(F1r[2]) - Fs[2]) * a.k.inv_ch;
     a.E[id] = E1r;
     a.Fx[id] = F1r[0];
     a.Fy[id] = F1r[1];
@@ -104,7 +113,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     a.mx[id] = mx;
     a.my[id] = my;
     a.mz[id] = mz;
-    return gas_T(rho, mx, my, mz, Eg, gam);
+    return gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
 }
 
 template <typename R, int OPK>
@@ -181,6 +190,12 @@ static void fill_args(m1_ctx *c, IArgs<R> &a, const Metric<R> &met, double dt)
     a.k.c = c->par.c;
     a.k.a = c->par.a_rad;
     a.k.gamma = c->par.gamma;
+    a.k.gm1 = c->par.gamma - 1.0;
+    a.k.inv_gm1 = 1.0 / a.k.gm1;
+    a.k.dt_ch = dt * c->c_hat;
+    a.k.dt_c = dt * c->par.c;
+    a.k.inv_ch = 1.0 / c->c_hat;
+    a.k.c_ratio = c->par.c * a.k.inv_ch;
     a.cnt = c->cnt;
 }
 

@@ -16,6 +16,8 @@ namespace m1 {
 // inside the 1e-12 parity tolerance; arguments are positive normal numbers).
 // FP32: hardware reciprocal and square root (about 1 ulp), inside 1e-5.
 template <typename R> struct Num;
+// rsqrt: FP64 as the square root of the refined reciprocal, FP32 from the
+// hardware estimate (about 1 ulp).
 template <> struct Num<double> {
     static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
     static __device__ __forceinline__ double rcp(double x)
@@ -25,10 +27,12 @@ template <> struct Num<double> {
         r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
         return r;
     }
+    static __device__ __forceinline__ double rsqrt(double x) { return __builtin_sqrt(rcp(x)); }
 };
 template <> struct Num<float> {
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 };
 
 // Closure quantities of one radiation state (E, F) seen from direction d:
@@ -158,19 +162,21 @@ __device__ __forceinline__ Wave<R> closure_wave_rt(R E, R Fx, R Fy, R Fz, int d)
     const bool clamped = f2 > R(1);
     f2 = clamped ? R(1) : f2;
     const R s = Num<R>::sqrt_(R(4) - R(3) * f2);
-    const R xi = (R(3) + R(4) * f2) * Num<R>::rcp(R(5) + R(2) * s);
-    const R iF2 = F2 > R(0) ? Num<R>::rcp(F2) : R(0);
+    // Levermore: xi = (3 + 4 f^2) / (5 + 2 s) = (5 - 2 s) / 3, so
+    // (1 - xi) / 2 = (s - 1) / 3 and (3 xi - 1) / 2 = 2 - s
+    const R iFn = F2 > R(0) ? Num<R>::rsqrt(F2) : R(0);
+    const R iF2 = iFn * iFn;
     const R Fd = d == 0 ? Fx : (d == 1 ? Fy : Fz);
     const R mu2 = Fd * Fd * iF2;
     R z2 = (R(2) / R(3)) * (R(4) - R(3) * f2 - s) + R(2) * mu2 * (R(2) - f2 - s);
     z2 = z2 < R(0) ? R(0) : z2;
     const R zeta = Num<R>::sqrt_(z2);
-    const R fmu = clamped ? Fd * Num<R>::sqrt_(iF2) : Fd * iE;
+    const R fmu = clamped ? Fd * iFn : Fd * iE;
     const R is = Num<R>::rcp(s);
     w.lm = (fmu - zeta) * is;
     w.lp = (fmu + zeta) * is;
-    const R iso = R(0.5) * (R(1) - xi) * E;
-    const R c = R(0.5) * (R(3) * xi - R(1)) * E * iF2 * Fd;
+    const R iso = (s - R(1)) * (R(1) / R(3)) * E;
+    const R c = (R(2) - s) * E * iF2 * Fd;
     w.phi[0] = Fd;
     w.phi[1] = c * Fx + (d == 0 ? iso : R(0));
     w.phi[2] = c * Fy + (d == 1 ? iso : R(0));
@@ -231,23 +237,20 @@ __device__ __forceinline__ R vanleer_fast(R dl, R dr)
     return p > R(0) ? (R(2) * p) * Num<R>::rcp(dl + dr) : R(0);
 }
 
-// HLL flux c_hat Phi* at the face between cells t-1 and t along d from the
-// stencil q(t-2), q(t-1), q(t), q(t+1): PLM van Leer slopes of the two donor
-// cells (w* = inverse centre spacings, hp/hm = centre-to-face offsets), the
-// f-preserving fix, both closures, the optical-depth-limited HLL speeds.
+// HLL flux c_hat Phi* at the face between donor cells b (left) and c (right)
+// along d from their states and van Leer slopes (sb, sc; per unit length):
+// face states q_b + s_b hp_b and q_c - s_c hm_c, the face fix, both
+// closures and the optical-depth-limited HLL (or LF) flux.
 template <typename R>
-__device__ __forceinline__ void face_flux(int d, const R qa[4], const R qb[4], const R qc[4], const R qd[4],
-                                          R wA, R wB, R wC, R hpL, R hmR, R tauL, R tauR, R c_hat, R out[4],
-                                          int recon = M1_RECON_FPRESERVE, int riemann = M1_RIEMANN_HLL)
+__device__ __forceinline__ void face_flux_s(int d, const R qb[4], const R qc[4], const R sb[4], const R sc[4],
+                                            R hpL, R hmR, R tauL, R tauR, R c_hat, R out[4],
+                                            int recon = M1_RECON_FPRESERVE, int riemann = M1_RIEMANN_HLL)
 {
     R UL[4], UR[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const R dAB = (qb[v] - qa[v]) * wA;
-        const R dBC = (qc[v] - qb[v]) * wB;
-        const R dCD = (qd[v] - qc[v]) * wC;
-        UL[v] = qb[v] + vanleer_fast(dAB, dBC) * hpL;
-        UR[v] = qc[v] - vanleer_fast(dBC, dCD) * hmR;
+        UL[v] = qb[v] + sb[v] * hpL;
+        UR[v] = qc[v] - sc[v] * hmR;
     }
     face_fix(recon, UL, qb);
     face_fix(recon, UR, qc);
@@ -279,6 +282,15 @@ __device__ __forceinline__ void face_flux(int d, const R qa[4], const R qb[4], c
 #pragma unroll
         for (int q = 0; q < 4; ++q) out[q] = c_hat * R(0.5) * (wl.phi[q] + wr.phi[q]);
     }
+}
+
+// van Leer slopes of the four fields of cell m from cells m-1, m, m+1 and the
+// inverse centre spacings wl = 1/(x_m - x_{m-1}), wr = 1/(x_{m+1} - x_m).
+template <typename R>
+__device__ __forceinline__ void slopes4(const R qm[4], const R q0[4], const R qp[4], R wl, R wr, R s[4])
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s[v] = vanleer_fast((q0[v] - qm[v]) * wl, (qp[v] - q0[v]) * wr);
 }
 
 } // namespace m1

@@ -42,6 +42,9 @@ struct OpacityParams {
 
 struct ImplicitConsts {
     double dt, c_hat, c, a, gamma;
+    double gm1, inv_gm1;        // gamma - 1 and its reciprocal
+    double dt_ch, dt_c;         // dt c_hat, dt c
+    double inv_ch, c_ratio;     // 1 / c_hat, c / c_hat
 };
 
 } // namespace m1

@@ -176,13 +176,41 @@ struct MlpWave {
 
 
 // ---------------------------------------------------------------------------
-// Inference variant with the 64x64 layer's operands staged in LDS once per
-// block and the first layer evaluated just in time, 16 units per k-step, so
-// a wavefront keeps only the 64 accumulators and one 16-unit chunk live.
+// Inference form.  A wavefront evaluates 64 inputs as two 32-sample column
+// tiles of the matrix-core products.  Lane l (g = l / 32, s = l % 32)
+// computes layer 1 directly in the B-operand layout: for k-step ks it
+// evaluates units 16 ks + 8 g + e (e = 0..7) for samples s and 32 + s, so
+// no hidden value changes lanes.  tanh is evaluated as 1 - 2 / (1 + 2^z)
+// with z = 2 log2(e) x; the factor is folded into the staged first-layer
+// weights and second-layer biases.  Operands and per-lane weights are staged
+// in LDS once per block.
 // ---------------------------------------------------------------------------
+
+constexpr float MLP_TANH_SCALE = 2.8853900817779268f;   // 2 / ln 2
+
+// tanh(z / MLP_TANH_SCALE); saturates to -1 and +1 for large |z|
+__device__ __forceinline__ float tanh_scaled(float z)
+{
+    return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z)), 1.0f);
+}
+
+// Split two floats into packed bfloat16 high parts (round to nearest even)
+// and packed bfloat16 remainders: a = hi_a + lo_a + O(2^-18 |a|).
+__device__ __forceinline__ void split_bf16x2(float a, float b, unsigned &hi, unsigned &lo)
+{
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 h = {to_bf16(a), to_bf16(b)};
+    hi = __builtin_bit_cast(unsigned, h);
+    const float ha = __uint_as_float(hi << 16), hb = __uint_as_float(hi & 0xffff0000u);
+    const bf16x2 l = {to_bf16(a - ha), to_bf16(b - hb)};
+    lo = __builtin_bit_cast(unsigned, l);
+}
 
 struct MlpShared {
     bf16x8 w2[2][2][4][64];   // [hi, lo][mt][ks][lane], 16 KiB
+    float w1[64][2];          // scaled W1
+    float b1[64];             // scaled b1
+    float4 ep[2][2][16];      // [g][mt][i]: scaled b2, W3[0], W3[1] of the slot's unit
 };
 
 __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, int tid, int nthreads)
@@ -194,69 +222,87 @@ __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, in
         dst[q] = hi[q];
         dst[512 + q] = lo[q];
     }
+    for (int q = tid; q < 64; q += nthreads) {
+        sh.w1[q][0] = MLP_TANH_SCALE * packed[MLP_OFF_W1 + 2 * q];
+        sh.w1[q][1] = MLP_TANH_SCALE * packed[MLP_OFF_W1 + 2 * q + 1];
+        sh.b1[q] = MLP_TANH_SCALE * packed[MLP_OFF_B1 + q];
+        const int g = q >> 5, mt = (q >> 4) & 1, i = q & 15;
+        const int u = MlpWave::unit(mt, i, g);
+        sh.ep[g][mt][i] = make_float4(MLP_TANH_SCALE * packed[MLP_OFF_B2 + u], packed[MLP_OFF_W3 + u],
+                                      packed[MLP_OFF_W3 + 64 + u], 0.0f);
+    }
 }
 
 __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShared &sh, float x0, float x1, int lane,
                                                    float &y0, float &y1)
 {
     const int g = lane >> 5;
+    // inputs of the two column tiles: lanes 0..31's samples, then lanes 32..63's
+    const float o0 = __shfl_xor(x0, 32), o1 = __shfl_xor(x1, 32);
+    const float xa[2] = {g ? o0 : x0, g ? x0 : o0};
+    const float xb[2] = {g ? o1 : x1, g ? x1 : o1};
     f32x16 acc[2][2];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[mt][nt][i] = 0.0f;
-#pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-        float h[16];
+        const int u0 = 16 * ks + 8 * g;
+        float wa[8], wb[8], bb[8];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int u = 16 * ks + e;
-            h[e] = fast_tanh(p[MLP_OFF_W1 + 2 * u] * x0 + p[MLP_OFF_W1 + 2 * u + 1] * x1 + p[MLP_OFF_B1 + u]);
+        for (int q = 0; q < 4; ++q) {
+            const float4 w = *reinterpret_cast<const float4 *>(&sh.w1[u0 + 2 * q][0]);
+            wa[2 * q] = w.x;
+            wb[2 * q] = w.y;
+            wa[2 * q + 1] = w.z;
+            wb[2 * q + 1] = w.w;
         }
-        bf16x8 own_h, own_l, oth_h, oth_l;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float mine = g ? h[8 + e] : h[e];
-            const float send = g ? h[e] : h[8 + e];
-            const float recv = __shfl_xor(send, 32);
-            const __bf16 mh = to_bf16(mine), rh = to_bf16(recv);
-            own_h[e] = mh;
-            own_l[e] = to_bf16(mine - float(mh));
-            oth_h[e] = rh;
-            oth_l[e] = to_bf16(recv - float(rh));
+        for (int q = 0; q < 2; ++q) {
+            const float4 b = *reinterpret_cast<const float4 *>(&sh.b1[u0 + 4 * q]);
+            bb[4 * q] = b.x;
+            bb[4 * q + 1] = b.y;
+            bb[4 * q + 2] = b.z;
+            bb[4 * q + 3] = b.w;
         }
-        const bf16x8 b0h = g == 0 ? own_h : oth_h, b0l = g == 0 ? own_l : oth_l;
-        const bf16x8 b1h = g == 1 ? own_h : oth_h, b1l = g == 1 ? own_l : oth_l;
+        bf16x8 bh[2], bl[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            float h[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                h[e] = tanh_scaled(__builtin_fmaf(wa[e], xa[nt], __builtin_fmaf(wb[e], xb[nt], bb[e])));
+            uint4 ph, pl;
+            split_bf16x2(h[0], h[1], ph.x, pl.x);
+            split_bf16x2(h[2], h[3], ph.y, pl.y);
+            split_bf16x2(h[4], h[5], ph.z, pl.z);
+            split_bf16x2(h[6], h[7], ph.w, pl.w);
+            bh[nt] = __builtin_bit_cast(bf16x8, ph);
+            bl[nt] = __builtin_bit_cast(bf16x8, pl);
+        }
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
             const bf16x8 ah = sh.w2[0][mt][ks][lane], al = sh.w2[1][mt][ks][lane];
-            acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b0h, acc[mt][0], 0, 0, 0);
-            acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b0l, acc[mt][0], 0, 0, 0);
-            acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b0h, acc[mt][0], 0, 0, 0);
-            acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b1h, acc[mt][1], 0, 0, 0);
-            acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b1l, acc[mt][1], 0, 0, 0);
-            acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b1h, acc[mt][1], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const f32x16 c0 = ks == 0 ? f32x16{} : acc[mt][nt];
+                f32x16 t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nt], c0, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nt], t, 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nt], t, 0, 0, 0);
+            }
         }
     }
-    float part[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+    float part[2][2] = {{0.f, 0.f}, {0.f, 0.f}};   // [nt][output]
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            // unit of this slot for lane group 0 / 1: uniform loads, then a select
-            const int u0 = MlpWave::unit(mt, i, 0), u1 = u0 + 4;
-            const float bb = g ? p[MLP_OFF_B2 + u1] : p[MLP_OFF_B2 + u0];
-            const float w0 = g ? p[MLP_OFF_W3 + u1] : p[MLP_OFF_W3 + u0];
-            const float w1 = g ? p[MLP_OFF_W3 + 64 + u1] : p[MLP_OFF_W3 + 64 + u0];
+            const float4 w = sh.ep[g][mt][i];
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
-                const float h2 = fast_tanh(acc[mt][nt][i] + bb);
-                part[nt][0] += w0 * h2;
-                part[nt][1] += w1 * h2;
+                const float h2 = tanh_scaled(__builtin_fmaf(acc[mt][nt][i], MLP_TANH_SCALE, w.x));
+                part[nt][0] = __builtin_fmaf(w.y, h2, part[nt][0]);
+                part[nt][1] = __builtin_fmaf(w.z, h2, part[nt][1]);
             }
         }
+    // the partner lane holds the other 32 units of the same samples
     const float s0 = g ? part[0][0] : part[1][0];
     const float s1 = g ? part[0][1] : part[1][1];
     const float r0 = __shfl_xor(s0, 32), r1 = __shfl_xor(s1, 32);

@@ -111,7 +111,7 @@ __device__ __forceinline__ void ignorable_div(const TArgs<R> &a, const R U[4], R
 // U* = U - dt div(Phi) + dt c_hat S_geo(U), then E >= floor and f <= 1
 // (counted), stored to the transported state.
 template <typename R, int GEOM>
-__device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], const R acc[4], int i, int j, int id)
+__device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], const R acc[4], R ir, R ct, int id)
 {
     R Us[4];
 #pragma unroll
@@ -123,20 +123,18 @@ __device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], con
         const R Fn = Num<R>::sqrt_(F2);
         R f = Fn * Num<R>::rcp(U[0]);
         f = f > R(1) ? R(1) : f;
+        // Levermore: (1 - xi) / 2 = (s - 1) / 3, (3 xi - 1) / 2 = 2 - s
         const R s = Num<R>::sqrt_(R(4) - R(3) * f * f);
-        const R xi = (R(3) + R(4) * f * f) * Num<R>::rcp(R(5) + R(2) * s);
         const R inv = Fn > R(0) ? Num<R>::rcp(Fn) : R(0);
         const R n_[3] = {U[1] * inv, U[2] * inv, U[3] * inv};
-        const R iso = R(0.5) * (R(1) - xi) * U[0];
-        const R an = R(0.5) * (R(3) * xi - R(1)) * U[0];
-        const R ir = a.m.inv_reff[i];
+        const R iso = (s - R(1)) * (R(1) / R(3)) * U[0];
+        const R an = (R(2) - s) * U[0];
         const R k_ = a.dt * a.c_hat * ir;
         if (GEOM == M1_CYLINDRICAL) {           // (R, phi, z)
             const R Ppp = an * n_[1] * n_[1] + iso, PRp = an * n_[0] * n_[1];
             Us[1] += k_ * Ppp;
             Us[2] -= k_ * PRp;
         } else {                                 // (r, theta, phi)
-            const R ct = a.m.cot_eff[j];
             const R Ptt = an * n_[1] * n_[1] + iso, Ppp = an * n_[2] * n_[2] + iso;
             const R Prt = an * n_[0] * n_[1], Prp = an * n_[0] * n_[2], Ptp = an * n_[1] * n_[2];
             Us[1] += k_ * (Ptt + Ppp);
@@ -188,19 +186,27 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
         ignorable_div<R, 2>(a, U, a.m.trA[2][i] * a.m.trB[2][j], acc);
     }
 
-    finish_cell<R, GEOM>(a, U, acc, i, j, id);
+    finish_cell<R, GEOM>(a, U, acc, GEOM == M1_CARTESIAN ? R(0) : a.m.inv_reff[i],
+                         GEOM == M1_SPHERICAL ? a.m.cot_eff[j] : R(0), id);
 }
 
 // ---------------------------------------------------------------------------
 // 3D tiled kernel: a block owns a TX x TY column of cells and marches along z
-// over a chunk of planes.  Per plane the state with a two-cell halo in x and
-// y is staged in LDS, every x and y face of the tile is computed once (one
-// face per thread per pass, faces of both directions in one flat loop), the
-// z face above the plane comes from a per-thread register window of four
-// planes, and the face fluxes are exchanged through LDS for the update.
+// over a chunk of planes.  Per plane: (1) the state with a two-cell halo in
+// x and y (cross-shaped, no corners) is staged in LDS; (2) van Leer slopes
+// of every cell that donates to a face of the tile are computed once per
+// direction (x: columns -1 .. TX, y: rows -1 .. TY) into LDS; (3) every x
+// and y face of the tile is computed once from the two donor states and
+// slopes (faces of both directions in one flat pass, direction chosen at run
+// time), and the z face above the plane from a per-thread register window
+// of four planes and the z slopes of planes k and k+1; (4) the update.
+// Each thread's slope and face assignments are the same in every plane, so
+// their metric factors are loaded once, before the march.
 // ---------------------------------------------------------------------------
 constexpr int TX = 32, TY = 8, HX = TX + 4, HY = TY + 4, NT = TX * TY;
 constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX, NHALO = 2 * (2 * TY + 2 * TX);
+constexpr int NXS = TY * (TX + 2), NYS = (TY + 2) * TX;
+constexpr int NSP = (NXS + NYS + NT - 1) / NT, NFP = (NXF + NYF + NT - 1) / NT;
 
 template <typename R, int GEOM, bool VARIANTS>
 __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
@@ -210,8 +216,12 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     const int riemann = VARIANTS ? a.riemann : int(M1_RIEMANN_HLL);
     __shared__ R sq[4][HY][HX];
     __shared__ R st[HY][HX];
+    __shared__ R ss[4][NXS + NYS];      // slopes: x tasks, then y tasks
     __shared__ R sfx[4][TY][TX + 1];
     __shared__ R sfy[4][TY + 1][TX];
+    R *const sqf = &sq[0][0][0];
+    const R *const stf = &st[0][0];
+    constexpr int QS = HY * HX, SS = NXS + NYS;
 
     // consecutive logical tiles share an XCD (blocks are dealt to XCDs round-robin)
     const int per = (nblocks + 7) / 8;
@@ -241,14 +251,93 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         hcol = gj * n0 + gi;
     }
 
+    // slope tasks: centre cell in sq (flat), neighbour stride, inverse spacings.
+    // Cells past the last ghost (m > n) feed no face and are skipped.
+    int s_ctr[NSP], s_str[NSP];
+    R s_wl[NSP], s_wr[NSP];
+    bool s_on[NSP];
+#pragma unroll
+    for (int p = 0; p < NSP; ++p) {
+        const int q = tid + p * NT;
+        s_on[p] = false;
+        s_ctr[p] = 2 * HX + 2;
+        s_str[p] = 1;
+        s_wl[p] = s_wr[p] = R(0);
+        if (q < NXS) {
+            const int r = q / (TX + 2), c = q % (TX + 2), m = x0 + c - 1;
+            if (m <= n0) {
+                s_on[p] = true;
+                s_ctr[p] = (r + 2) * HX + c + 1;
+                s_wl[p] = a.m.winv[0][m + 2];
+                s_wr[p] = a.m.winv[0][m + 3];
+            }
+        } else if (q < NXS + NYS) {
+            const int qq = q - NXS, r = qq / TX, c = qq % TX, m = y0 + r - 1;
+            if (m <= n1) {
+                s_on[p] = true;
+                s_ctr[p] = (r + 1) * HX + c + 2;
+                s_str[p] = HX;
+                s_wl[p] = a.m.winv[1][m + 2];
+                s_wr[p] = a.m.winv[1][m + 3];
+            }
+        }
+    }
+    // face tasks: direction, left donor in sq, its slope in ss, flux slot,
+    // centre-to-face offsets of the two donors
+    int f_d[NFP], f_b[NFP], f_sb[NFP], f_o[NFP];
+    R f_hp[NFP], f_hm[NFP];
+    bool f_on[NFP];
+#pragma unroll
+    for (int p = 0; p < NFP; ++p) {
+        const int q = tid + p * NT;
+        f_on[p] = false;
+        f_d[p] = 0;
+        f_b[p] = f_sb[p] = f_o[p] = 0;
+        f_hp[p] = f_hm[p] = R(0);
+        if (q < NXF) {
+            const int row = q / (TX + 1), fo = q % (TX + 1), g = x0 + fo;
+            if (g <= n0 && y0 + row < n1) {
+                f_on[p] = true;
+                f_b[p] = (row + 2) * HX + fo + 1;
+                f_sb[p] = row * (TX + 2) + fo;
+                f_o[p] = row * (TX + 1) + fo;
+                f_hp[p] = a.m.hp[0][g + 1];
+                f_hm[p] = a.m.hm[0][g + 2];
+            }
+        } else if (q < NXF + NYF) {
+            const int qq = q - NXF, go = qq / TX, cl = qq % TX, g = y0 + go;
+            if (g <= n1 && x0 + cl < n0) {
+                f_on[p] = true;
+                f_d[p] = 1;
+                f_b[p] = (go + 1) * HX + cl + 2;
+                f_sb[p] = NXS + go * TX + cl;
+                f_o[p] = go * TX + cl;
+                f_hp[p] = a.m.hp[1][g + 1];
+                f_hm[p] = a.m.hm[1][g + 2];
+            }
+        }
+    }
+    // update factors of the thread's column
+    R axl = R(0), axh = R(0), ayl = R(0), ayh = R(0), tr2 = R(0), ir = R(0), ct = R(0);
+    if (live) {
+        axl = a.m.alo[0][i];
+        axh = a.m.ahi[0][i];
+        const R tr1 = a.m.trA[1][i];
+        ayl = a.m.alo[1][j] * tr1;
+        ayh = a.m.ahi[1][j] * tr1;
+        tr2 = a.m.trA[2][i] * a.m.trB[2][j];
+        if (GEOM != M1_CARTESIAN) ir = a.m.inv_reff[i];
+        if (GEOM == M1_SPHERICAL) ct = a.m.cot_eff[j];
+    }
+
     const int bz0 = a.bc[2][0], bz1 = a.bc[2][1];
     auto zlin = [&](int kk, int c) { return map_index(kk, n2, bz0, bz1) * plane + c; };
     const R *wz = a.m.winv[2], *hpz = a.m.hp[2], *hmz = a.m.hm[2];
 
-    // register window of the thread's column: planes k-1 .. k+2
-    R W[4][4], T1, T2, Fzlo[4], Fzhi[4];
+    // register window of the thread's column: planes k-1 .. k+2, z slope of plane k
+    R W[4][4], T1, T2, Fzlo[4], Fzhi[4], Sz0[4];
     {
-        R Q0[4];
+        R Q0[4], Szm[4];
         load4(a, zlin(z0 - 2, col), Q0);
         load4(a, zlin(z0 - 1, col), W[0]);
         load4(a, zlin(z0, col), W[1]);
@@ -257,8 +346,9 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         const R Tm = a.tau[zlin(z0 - 1, col)];
         T1 = a.tau[zlin(z0, col)];
         T2 = a.tau[zlin(z0 + 1, col)];
-        face_flux<R>(2, Q0, W[0], W[1], W[2], wz[z0 + 1], wz[z0 + 2], wz[z0 + 3], hpz[z0 + 1], hmz[z0 + 2],
-                     Tm, T1, a.c_hat, Fzlo, recon, riemann);
+        slopes4(Q0, W[0], W[1], wz[z0 + 1], wz[z0 + 2], Szm);
+        slopes4(W[0], W[1], W[2], wz[z0 + 2], wz[z0 + 3], Sz0);
+        face_flux_s<R>(2, W[0], W[1], Szm, Sz0, hpz[z0 + 1], hmz[z0 + 2], Tm, T1, a.c_hat, Fzlo, recon, riemann);
     }
 
     for (int k = z0; k < z1; ++k) {
@@ -281,60 +371,63 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         }
         __syncthreads();
 
+        // slopes of the x and y donor cells
+#pragma unroll
+        for (int p = 0; p < NSP; ++p) {
+            if (!s_on[p]) continue;
+            R qm[4], q0[4], qp[4], sl[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                qm[v] = sqf[v * QS + s_ctr[p] - s_str[p]];
+                q0[v] = sqf[v * QS + s_ctr[p]];
+                qp[v] = sqf[v * QS + s_ctr[p] + s_str[p]];
+            }
+            slopes4(qm, q0, qp, s_wl[p], s_wr[p], sl);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ss[v][tid + p * NT] = sl[v];
+        }
+        // z slope of plane k+1
+        R Sz1[4];
+        slopes4(W[1], W[2], W[3], wz[k + 3], wz[k + 4], Sz1);
+        __syncthreads();
+
         // x faces (left face of column f) and y faces (lower face of row g)
-        for (int q = tid; q < NXF + NYF; q += NT) {
-            int d, r0, c0, dr, dc, gidx;
-            if (q < NXF) {
-                const int row = q / (TX + 1), fo = q % (TX + 1);
-                gidx = x0 + fo;
-                if (gidx > n0 || y0 + row >= n1) continue;
-                d = 0; r0 = row + 2; c0 = fo; dr = 0; dc = 1;
-            } else {
-                const int qq = q - NXF, go = qq / TX, cl = qq % TX;
-                gidx = y0 + go;
-                if (gidx > n1 || x0 + cl >= n0) continue;
-                d = 1; r0 = go; c0 = cl + 2; dr = 1; dc = 0;
+#pragma unroll
+        for (int p = 0; p < NFP; ++p) {
+            if (!f_on[p]) continue;
+            const int d = f_d[p], b = f_b[p], sb = f_sb[p];
+            const int qst = d ? HX : 1, sst = d ? TX : 1;
+            R qb[4], qc[4], slb[4], slc[4], fl[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                qb[v] = sqf[v * QS + b];
+                qc[v] = sqf[v * QS + b + qst];
+                slb[v] = ss[v][sb];
+                slc[v] = ss[v][sb + sst];
             }
-            R qs[4][4], tl, tr;
+            face_flux_s<R>(d, qb, qc, slb, slc, f_hp[p], f_hm[p], stf[b], stf[b + qst], a.c_hat, fl, recon, riemann);
+            R *dst = d ? &sfy[0][0][0] : &sfx[0][0][0];
+            const int fs = d ? (TY + 1) * TX : TY * (TX + 1);
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) qs[s2][v] = sq[v][r0 + s2 * dr][c0 + s2 * dc];
-            tl = st[r0 + dr][c0 + dc];
-            tr = st[r0 + 2 * dr][c0 + 2 * dc];
-            const R *wv = a.m.winv[d], *hpv = a.m.hp[d], *hmv = a.m.hm[d];
-            R fl[4];
-            face_flux<R>(d, qs[0], qs[1], qs[2], qs[3], wv[gidx + 1], wv[gidx + 2], wv[gidx + 3], hpv[gidx + 1],
-                         hmv[gidx + 2], tl, tr, a.c_hat, fl, recon, riemann);
-            if (d == 0) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sfx[v][r0 - 2][c0] = fl[v];
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sfy[v][r0][c0 - 2] = fl[v];
-            }
+            for (int v = 0; v < 4; ++v) dst[v * fs + f_o[p]] = fl[v];
         }
         // z face above the plane from the register window
-        face_flux<R>(2, W[0], W[1], W[2], W[3], wz[k + 2], wz[k + 3], wz[k + 4], hpz[k + 2], hmz[k + 3], T1, T2,
-                     a.c_hat, Fzhi, recon, riemann);
+        face_flux_s<R>(2, W[1], W[2], Sz0, Sz1, hpz[k + 2], hmz[k + 3], T1, T2, a.c_hat, Fzhi, recon, riemann);
         __syncthreads();
 
         if (live) {
             R acc[4];
-            const R axl = a.m.alo[0][i], axh = a.m.ahi[0][i];
-            const R tr1 = a.m.trA[1][i];
-            const R ayl = a.m.alo[1][j] * tr1, ayh = a.m.ahi[1][j] * tr1;
-            const R tr2 = a.m.trA[2][i] * a.m.trB[2][j];
             const R azl = a.m.alo[2][k] * tr2, azh = a.m.ahi[2][k] * tr2;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 acc[v] = (axh * sfx[v][ly][lx + 1] - axl * sfx[v][ly][lx]) +
                          (ayh * sfy[v][ly + 1][lx] - ayl * sfy[v][ly][lx]) + (azh * Fzhi[v] - azl * Fzlo[v]);
-            finish_cell<R, GEOM>(a, W[1], acc, i, j, (k * n1 + j) * n0 + i);
+            finish_cell<R, GEOM>(a, W[1], acc, ir, ct, (k * n1 + j) * n0 + i);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             Fzlo[v] = Fzhi[v];
+            Sz0[v] = Sz1[v];
             W[0][v] = W[1][v];
             W[1][v] = W[2][v];
             W[2][v] = W[3][v];
