@@ -177,13 +177,20 @@ struct MlpWave {
 
 // ---------------------------------------------------------------------------
 // Inference form.  A wavefront evaluates 64 inputs as two 32-sample column
-// tiles of the matrix-core products.  Lane l (g = l / 32, s = l % 32)
-// computes layer 1 directly in the B-operand layout: for k-step ks it
-// evaluates units 16 ks + 8 g + e (e = 0..7) for samples s and 32 + s, so
-// no hidden value changes lanes.  tanh is evaluated as 1 - 2 / (1 + 2^z)
-// with z = 2 log2(e) x; the factor is folded into the staged first-layer
-// weights and second-layer biases.  Operands and per-lane weights are staged
-// in LDS once per block.
+// tiles of the matrix-core products, both hidden layers on the matrix cores.
+//
+// Layer 1 (K = 16 per 32-unit tile): inputs and weights are split exactly
+// into three bfloat16 pieces (h + m + l, 24 significant bits), and the six
+// cross terms hh, hm, mh, hl, lh, mm of each weight-input product plus the
+// three bias pieces fill the K slots, so the pre-activation carries
+// single-precision accuracy (the dropped terms are below 2^-24 relative).
+// The rows of W1 are permuted (bits 2 and 3 of the row index swapped) so
+// that each lane's accumulator slots 8 hs .. 8 hs + 7 are exactly the units
+// 16 ks + 8 g + e (ks = 2 mt + hs) that layer 2 wants from the lane as its
+// B operand: no hidden value changes lanes.
+//
+// tanh is evaluated as 1 - 2 / (1 + 2^z) with z = 2 log2(e) x; the factor
+// is folded into the staged first-layer weights and second-layer biases.
 // ---------------------------------------------------------------------------
 
 constexpr float MLP_TANH_SCALE = 2.8853900817779268f;   // 2 / ln 2
@@ -194,22 +201,41 @@ __device__ __forceinline__ float tanh_scaled(float z)
     return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z)), 1.0f);
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 // Split two floats into packed bfloat16 high parts (round to nearest even)
 // and packed bfloat16 remainders: a = hi_a + lo_a + O(2^-18 |a|).
 __device__ __forceinline__ void split_bf16x2(float a, float b, unsigned &hi, unsigned &lo)
 {
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-    const bf16x2 h = {to_bf16(a), to_bf16(b)};
+    const bf16x2_t h = {to_bf16(a), to_bf16(b)};
     hi = __builtin_bit_cast(unsigned, h);
     const float ha = __uint_as_float(hi << 16), hb = __uint_as_float(hi & 0xffff0000u);
-    const bf16x2 l = {to_bf16(a - ha), to_bf16(b - hb)};
+    const bf16x2_t l = {to_bf16(a - ha), to_bf16(b - hb)};
     lo = __builtin_bit_cast(unsigned, l);
+}
+
+// Exact three-piece split v = h + m + l (bfloat16 each), returned packed as
+// (h, m) and (h, l).
+__device__ __forceinline__ void split3_bf16(float v, unsigned &hm, unsigned &hl)
+{
+    const float h = __uint_as_float(__builtin_bit_cast(unsigned short, to_bf16(v)) << 16);
+    const float r = v - h;
+    const bf16x2_t p0 = {to_bf16(v), to_bf16(r)};
+    hm = __builtin_bit_cast(unsigned, p0);
+    const float r2 = r - __uint_as_float(hm & 0xffff0000u);
+    const bf16x2_t p1 = {to_bf16(v), to_bf16(r2)};
+    hl = __builtin_bit_cast(unsigned, p1);
+}
+
+// row of a 32-row layer-1 tile -> hidden unit it computes (bits 2, 3 swapped)
+__host__ __device__ constexpr int mlp_l1_unit(int mt, int r)
+{
+    return 32 * mt + (r & 0x13) + ((r & 4) << 1) + ((r & 8) >> 1);
 }
 
 struct MlpShared {
     bf16x8 w2[2][2][4][64];   // [hi, lo][mt][ks][lane], 16 KiB
-    float w1[64][2];          // scaled W1
-    float b1[64];             // scaled b1
+    bf16x8 w1[2][64];         // layer-1 A operand: [mt][lane]
     float4 ep[2][2][16];      // [g][mt][i]: scaled b2, W3[0], W3[1] of the slot's unit
 };
 
@@ -222,10 +248,26 @@ __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, in
         dst[q] = hi[q];
         dst[512 + q] = lo[q];
     }
+    for (int q = tid; q < 128; q += nthreads) {
+        // layer-1 A operand of lane l in tile mt: row l % 32, K = 8 (l / 32) + e
+        const int mt = q >> 6, l = q & 63, g = l >> 5;
+        const int u = mlp_l1_unit(mt, l & 31);
+        const float w = MLP_TANH_SCALE * packed[MLP_OFF_W1 + 2 * u + g];
+        const float bias = MLP_TANH_SCALE * packed[MLP_OFF_B1 + u];
+        unsigned whm, whl, bhm, bhl;
+        split3_bf16(w, whm, whl);
+        split3_bf16(bias, bhm, bhl);
+        const unsigned wh = whm & 0xffffu, wm = whm >> 16, wl = whl >> 16;
+        const unsigned bh = bhm & 0xffffu, bm = bhm >> 16, bl = bhl >> 16;
+        // K slots: Wh Wh Wm Wh Wl Wm | bias (g = 0: bh bm; g = 1: bl 0)
+        uint4 v;
+        v.x = wh | (wh << 16);
+        v.y = wm | (wh << 16);
+        v.z = wl | (wm << 16);
+        v.w = g ? bl : (bh | (bm << 16));
+        sh.w1[mt][l] = __builtin_bit_cast(bf16x8, v);
+    }
     for (int q = tid; q < 64; q += nthreads) {
-        sh.w1[q][0] = MLP_TANH_SCALE * packed[MLP_OFF_W1 + 2 * q];
-        sh.w1[q][1] = MLP_TANH_SCALE * packed[MLP_OFF_W1 + 2 * q + 1];
-        sh.b1[q] = MLP_TANH_SCALE * packed[MLP_OFF_B1 + q];
         const int g = q >> 5, mt = (q >> 4) & 1, i = q & 15;
         const int u = MlpWave::unit(mt, i, g);
         sh.ep[g][mt][i] = make_float4(MLP_TANH_SCALE * packed[MLP_OFF_B2 + u], packed[MLP_OFF_W3 + u],
@@ -237,55 +279,58 @@ __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShar
                                                    float &y0, float &y1)
 {
     const int g = lane >> 5;
-    // inputs of the two column tiles: lanes 0..31's samples, then lanes 32..63's
-    const float o0 = __shfl_xor(x0, 32), o1 = __shfl_xor(x1, 32);
-    const float xa[2] = {g ? o0 : x0, g ? x0 : o0};
-    const float xb[2] = {g ? o1 : x1, g ? x1 : o1};
+    // layer-1 B operand: lanes of group 0 supply input 0, group 1 input 1, of
+    // sample l % 32 (tile 0) and 32 + l % 32 (tile 1)
+    const float mine = g ? x1 : x0;
+    const float recv = __shfl_xor(g ? x0 : x1, 32);
+    const float xin[2] = {g ? recv : mine, g ? mine : recv};
+    bf16x8 b1op[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        unsigned hm, hl;
+        split3_bf16(xin[nt], hm, hl);
+        // K slots: xh xm xh xl xh xm | 1 1 (group 0) or 1 0 (group 1)
+        uint4 v;
+        v.x = hm;
+        v.y = hl;
+        v.z = hm;
+        v.w = g ? 0x00003f80u : 0x3f803f80u;
+        b1op[nt] = __builtin_bit_cast(bf16x8, v);
+    }
     f32x16 acc[2][2];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        const int u0 = 16 * ks + 8 * g;
-        float wa[8], wb[8], bb[8];
+    for (int m1 = 0; m1 < 2; ++m1) {
+        const bf16x8 a1 = sh.w1[m1][lane];
+        f32x16 z1[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 w = *reinterpret_cast<const float4 *>(&sh.w1[u0 + 2 * q][0]);
-            wa[2 * q] = w.x;
-            wb[2 * q] = w.y;
-            wa[2 * q + 1] = w.z;
-            wb[2 * q + 1] = w.w;
-        }
+        for (int nt = 0; nt < 2; ++nt) z1[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1op[nt], f32x16{}, 0, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const float4 b = *reinterpret_cast<const float4 *>(&sh.b1[u0 + 4 * q]);
-            bb[4 * q] = b.x;
-            bb[4 * q + 1] = b.y;
-            bb[4 * q + 2] = b.z;
-            bb[4 * q + 3] = b.w;
-        }
-        bf16x8 bh[2], bl[2];
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            float h[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                h[e] = tanh_scaled(__builtin_fmaf(wa[e], xa[nt], __builtin_fmaf(wb[e], xb[nt], bb[e])));
-            uint4 ph, pl;
-            split_bf16x2(h[0], h[1], ph.x, pl.x);
-            split_bf16x2(h[2], h[3], ph.y, pl.y);
-            split_bf16x2(h[4], h[5], ph.z, pl.z);
-            split_bf16x2(h[6], h[7], ph.w, pl.w);
-            bh[nt] = __builtin_bit_cast(bf16x8, ph);
-            bl[nt] = __builtin_bit_cast(bf16x8, pl);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            const bf16x8 ah = sh.w2[0][mt][ks][lane], al = sh.w2[1][mt][ks][lane];
+        for (int hs = 0; hs < 2; ++hs) {
+            const int ks = 2 * m1 + hs;
+            bf16x8 bh[2], bl[2];
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
-                const f32x16 c0 = ks == 0 ? f32x16{} : acc[mt][nt];
-                f32x16 t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nt], c0, 0, 0, 0);
-                t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nt], t, 0, 0, 0);
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nt], t, 0, 0, 0);
+                float h[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[e] = tanh_scaled(z1[nt][8 * hs + e]);
+                uint4 ph, pl;
+                split_bf16x2(h[0], h[1], ph.x, pl.x);
+                split_bf16x2(h[2], h[3], ph.y, pl.y);
+                split_bf16x2(h[4], h[5], ph.z, pl.z);
+                split_bf16x2(h[6], h[7], ph.w, pl.w);
+                bh[nt] = __builtin_bit_cast(bf16x8, ph);
+                bl[nt] = __builtin_bit_cast(bf16x8, pl);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const bf16x8 ah = sh.w2[0][mt][ks][lane], al = sh.w2[1][mt][ks][lane];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const f32x16 c0 = ks == 0 ? f32x16{} : acc[mt][nt];
+                    f32x16 t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nt], c0, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nt], t, 0, 0, 0);
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nt], t, 0, 0, 0);
+                }
             }
         }
     }
