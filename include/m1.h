@@ -13,7 +13,7 @@
  *   m1_step_implicit   per-cell backward-Euler radiation-matter exchange,
  *                      the 2x2 system of Eq. implicit_matrix, flux damping of
  *                      Eq. source_discrete2 and the gas update from the
- *                      rescaled conservation laws (Sect. 2.7, 2.8).
+ *                      rescaled conservation laws (Sect. 2.6, 2.7).
  *
  * Conventions
  *   - F is the paper's radiation flux that carries the 1/c factor
@@ -73,7 +73,7 @@ typedef struct {
 
 /* Physical and numerical parameters (m1_params_default fills them):
  * c       true speed of light (default: c_hat), enters the gas energy
- *         exchange (Eq. internal) and the rescaled energy total (Sect. 2.7)
+ *         exchange (Eq. internal) and the rescaled energy total (Sect. 2.6)
  * a_rad   radiation constant a_R (default 1)
  * gamma   adiabatic index; C_v = rho / (gamma - 1) per volume (default 5/3)
  * precision  M1_P64 (all FP64) or M1_F32 (FP32 radiation storage and

@@ -43,7 +43,7 @@ void m1o_eddington(double E, double Fx, double Fy, double Fz, double *f, double 
 }
 
 /* Extreme eigenvalues lambda_{1,3} = (f cos(theta) -+ zeta) / sqrt(4 - 3 f^2)
- * of the M1 system along direction d (Sect. 2.6); cos(theta) = n_d. */
+ * of the M1 system along direction d (Sect. 2.5); cos(theta) = n_d. */
 void m1o_speeds(double E, double Fx, double Fy, double Fz, int d, double *lm, double *lp)
 {
     double F[3] = {Fx, Fy, Fz}, n[3], f;
@@ -69,7 +69,7 @@ void m1o_flux(double E, double Fx, double Fy, double Fz, int d, double phi[4])
     for (int a = 0; a < 3; ++a) phi[1 + a] = E * D[3 * a + d];
 }
 
-/* HLL flux (Sect. 2.5) with the Sect. 2.6 signal speeds and the optical-depth
+/* HLL flux (Sect. 2.5) with the Sect. 2.5 signal speeds and the optical-depth
  * limiter: lambda_L = min of the left-going speeds of both states, lambda_R =
  * max of the right-going ones, then clamped to -+4/(3 tau) when tau > 0.
  * Returns c_hat * Phi*. */

@@ -1,6 +1,6 @@
 /*
  * implicit.c -- oracle: opacity sources and the implicit radiation-matter
- * step (Sect. 2.8).  Test infrastructure only.
+ * step (Sect. 2.7).  Test infrastructure only.
  */
 #include <float.h>
 #include <math.h>
@@ -88,15 +88,15 @@ void m1o_opacity_many(const m1o_problem *p, long n, const double *rho, const dou
  * out[0], out[1]: E', T' in a cancellation-free arrangement of Cramer's
  * rule; out[2], out[3]: the same from the literal Cramer numerators. */
 void m1o_implicit_cell(double Es, double Cv, double T, double kP, double rho, double dt,
-                       double c_hat, double c, double a, double out[4])
+                       double c_hat, double c, double a, double S, double out[4])
 {
     double gr = dt * c_hat * kP * rho;
     double g = dt * c * kP * rho;
     double aT3 = a * T * T * T, aT4 = aT3 * T;
     double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
-    out[0] = (Cv * (Es + gr * aT4) + 4.0 * g * aT3 * Es) / det;
-    out[1] = (Cv * T * (1.0 + gr) + 3.0 * g * aT4 + g * Es) / det;
-    double b0 = Es - 3.0 * gr * aT4, b1 = Cv * T + 3.0 * g * aT4;
+    out[0] = (Cv * (Es + gr * aT4) + 4.0 * aT3 * (g * Es + gr * S)) / det;
+    out[1] = (Cv * T * (1.0 + gr) + 3.0 * g * aT4 + g * Es + (1.0 + gr) * S) / det;
+    double b0 = Es - 3.0 * gr * aT4, b1 = Cv * T + 3.0 * g * aT4 + S;
     double m00 = 1.0 + gr, m01 = -4.0 * gr * aT3, m10 = -g, m11 = Cv + 4.0 * g * aT3;
     out[2] = (b0 * m11 - m01 * b1) / det;
     out[3] = (m00 * b1 - m10 * b0) / det;
@@ -117,18 +117,23 @@ int m1o_implicit(const m1o_problem *p, double dt, const double *const star[4],
         double chi = kR + p->sigma;
         double Es = star[0][id];
         double Fs[3] = {star[1][id], star[2][id], star[3][id]};
+        /* irradiation heating deposited in this step (Sect. 2.8: -div F_irr dt
+         * in the S_1 row and in the conserved total) */
+        double S = p->irr ? p->irr[id] * dt : 0.0;
         double r[4];
-        m1o_implicit_cell(Es, Cv, T, kP, rho, dt, p->c_hat, p->c, p->a_rad, r);
+        m1o_implicit_cell(Es, Cv, T, kP, rho, dt, p->c_hat, p->c, p->a_rad, S, r);
         /* both algebraic forms must agree within their rounding bound */
-        {
+        if (!p->absorb_only) {
             double gr = dt * p->c_hat * kP * rho, g = dt * p->c * kP * rho;
             double aT3 = p->a_rad * T * T * T, aT4 = aT3 * T;
             double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
-            double b0 = Es - 3.0 * gr * aT4, b1 = Cv * T + 3.0 * g * aT4;
+            double b0 = Es - 3.0 * gr * aT4, b1 = Cv * T + 3.0 * g * aT4 + S;
             double scale = (fabs(b0 * (Cv + 4.0 * g * aT3)) + fabs(4.0 * gr * aT3 * b1)) / det;
             if (fabs(r[0] - r[2]) > 64.0 * DBL_EPSILON * scale + DBL_MIN) ++mism;
         }
-        double E1 = r[0];
+        /* absorption only (shadow test of Sect. 3.3): no emission by the gas,
+         * E' = E* / (1 + gamma_abs,red) */
+        double E1 = p->absorb_only ? Es / (1.0 + dt * p->c_hat * kP * rho) : r[0];
         double damp = 1.0 + dt * p->c_hat * chi * rho;     /* Eq. source_discrete2 */
         double F1[3] = {Fs[0] / damp, Fs[1] / damp, Fs[2] / damp};
         double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
@@ -138,8 +143,8 @@ int m1o_implicit(const m1o_problem *p, double dt, const double *const star[4],
             ++ffx;
         }
         /* gas from the rescaled conservation laws E + (c/c_hat) E_r and
-         * rho v + F_r / c_hat (Sect. 2.7) */
-        st[8][id] = Eg - (p->c / p->c_hat) * (E1 - Es);
+         * rho v + F_r / c_hat (Sect. 2.6) */
+        st[8][id] = Eg + S - (p->c / p->c_hat) * (E1 - Es);
         st[5][id] = mx - (F1[0] - Fs[0]) / p->c_hat;
         st[6][id] = my - (F1[1] - Fs[1]) / p->c_hat;
         st[7][id] = mz - (F1[2] - Fs[2]) / p->c_hat;

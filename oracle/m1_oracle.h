@@ -7,9 +7,9 @@
  *
  * It computes, in double precision and in the order the method states it,
  * one explicit transport step (Sect. 2.5 reconstruction + f-preserving face
- * fix, Sect. 2.6 signal speeds + optical-depth limiter, HLL fluxes,
+ * fix, Sect. 2.5 signal speeds + optical-depth limiter, HLL fluxes,
  * conservative update in Cartesian / cylindrical / spherical coordinates)
- * and one implicit radiation-matter step (Sect. 2.8, Eq. implicit_matrix),
+ * and one implicit radiation-matter step (Sect. 2.7, Eq. implicit_matrix),
  * plus the opacity sources (constant, power law, bilinear table, MLP).
  *
  * Array layout: cell (i, j, k) along (d0, d1, d2) lives at ((k*n1)+j)*n0+i.
@@ -23,7 +23,10 @@ extern "C" {
 #endif
 
 enum { M1O_CARTESIAN = 0, M1O_CYLINDRICAL = 1, M1O_SPHERICAL = 2 };
-enum { M1O_PERIODIC = 0, M1O_OUTFLOW = 1 };
+/* boundaries: periodic wrap, outflow (zero-gradient copy), reflective
+ * (mirror image with the normal flux component reversed), fixed (a given
+ * ghost state, e.g. an injected beam) */
+enum { M1O_PERIODIC = 0, M1O_OUTFLOW = 1, M1O_REFLECT = 2, M1O_FIXED = 3 };
 enum { M1O_CONST = 0, M1O_POWERLAW = 1, M1O_TABLE = 2, M1O_MLP = 3 };
 /* face treatment after reconstruction (Sect. 2.5, 3.2) and Riemann solver */
 enum { M1O_RECON_FPRESERVE = 0, M1O_RECON_PLUTO = 1, M1O_RECON_CLIP = 2 };
@@ -50,6 +53,9 @@ typedef struct {
     int mlp_bf16;             /* 1: round layer-2 operands like the GPU */
     int recon;                /* M1O_RECON_* */
     int riemann;              /* M1O_HLL or M1O_LF */
+    double bc_state[3][2][4]; /* ghost (E, Fx, Fy, Fz) of M1O_FIXED sides */
+    const double *irr;        /* per-cell irradiation heating -div F_irr, or NULL */
+    int absorb_only;          /* 1: radiation is absorbed, never emitted */
 } m1o_problem;
 
 /* --- closure, speeds, fluxes (Sect. 2.1, 2.5, 2.6) ------------------------ */
@@ -80,7 +86,7 @@ int m1o_run_rk2(const m1o_problem *p, double dt, int nsteps, double *const st[9]
 
 /* --- single-cell implicit solve (both algebraic forms) -------------------- */
 void m1o_implicit_cell(double Es, double Cv, double T, double kP, double rho, double dt,
-                       double c_hat, double c, double a, double out[4]);
+                       double c_hat, double c, double a, double S, double out[4]);
 
 /* --- opacity -------------------------------------------------------------- */
 void m1o_opacity(const m1o_problem *p, double rho, double T, double *kP, double *kR);

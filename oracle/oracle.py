@@ -57,6 +57,9 @@ class Problem(C.Structure):
         ("mlp_bf16", C.c_int),
         ("recon", C.c_int),
         ("riemann", C.c_int),
+        ("bc_state", ((C.c_double * 4) * 2) * 3),
+        ("irr", C.POINTER(C.c_double)),
+        ("absorb_only", C.c_int),
     ]
 
 
@@ -91,7 +94,7 @@ def lib():
         L.m1o_implicit.argtypes = [C.POINTER(Problem), C.c_double, pp, pp, cnt]
         L.m1o_run.argtypes = [C.POINTER(Problem), C.c_double, C.c_int, pp, cnt]
         L.m1o_run_rk2.argtypes = [C.POINTER(Problem), C.c_double, C.c_int, pp, cnt]
-        L.m1o_implicit_cell.argtypes = [C.c_double] * 9 + [_dp]
+        L.m1o_implicit_cell.argtypes = [C.c_double] * 10 + [_dp]
         L.m1o_opacity.argtypes = [C.POINTER(Problem), C.c_double, C.c_double, _dp, _dp]
         L.m1o_opacity_many.argtypes = [C.POINTER(Problem), C.c_long, _dp, _dp, _dp, _dp]
         L.m1o_mlp_nparam.restype = C.c_int
@@ -133,6 +136,20 @@ class Oracle:
         P.gamma, P.e_floor = prob.gamma, prob.e_floor
         P.recon = getattr(prob, "recon", 0)
         P.riemann = getattr(prob, "riemann", 0)
+        P.absorb_only = int(getattr(prob, "absorb_only", 0))
+        bs = getattr(prob, "bc_state", None)
+        if bs is not None:
+            for d in range(3):
+                for side in range(2):
+                    if bs[d][side] is not None:
+                        for v in range(4):
+                            P.bc_state[d][side][v] = float(bs[d][side][v])
+        irr = getattr(prob, "irr", None)
+        if irr is not None:
+            q = np.ascontiguousarray(irr, dtype=np.float64).ravel()
+            assert q.size == int(np.prod(prob.n))
+            self._keep.append(q)
+            P.irr = _ptr(q)
         op = prob.opacity
         P.opac_kind = op["kind"]
         P.sigma = op.get("sigma", 0.0)
@@ -297,10 +314,12 @@ def lf(UL, UR, d, tau=0.0, c_hat=1.0):
     return out
 
 
-def implicit_cell(Es, Cv, T, kP, rho, dt, c_hat, c, a=1.0):
+def implicit_cell(Es, Cv, T, kP, rho, dt, c_hat, c, a=1.0, S=0.0):
+    """Single-cell implicit solve; S = irradiation energy deposited in the
+    step (added to the S_1 row)."""
     out = np.zeros(4)
     lib().m1o_implicit_cell(float(Es), float(Cv), float(T), float(kP), float(rho), float(dt),
-                            float(c_hat), float(c), float(a), _ptr(out))
+                            float(c_hat), float(c), float(a), float(S), _ptr(out))
     return out
 
 

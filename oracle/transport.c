@@ -84,28 +84,56 @@ double m1o_max_dt(const m1o_problem *p, double cfl)
 /* boundary ghosts                                                          */
 /* ------------------------------------------------------------------------ */
 
-/* Interior index that supplies ghost index t along d: periodic wrap, or the
- * nearest interior cell for outflow (zero-gradient copy). */
+/* Interior index that supplies ghost index t along d: periodic wrap, the
+ * mirror image for a reflective side, or the nearest interior cell for
+ * outflow (zero-gradient copy) and fixed sides (whose state is replaced, see
+ * ghost_state; the optical depth is the nearest interior cell's). */
 static int src_index(const m1o_problem *p, int d, int t)
 {
     int n = p->n[d];
     if (t >= 0 && t < n) return t;
-    if (p->bc[d][t < 0 ? 0 : 1] == M1O_PERIODIC) return ((t % n) + n) % n;
+    int bc = p->bc[d][t < 0 ? 0 : 1];
+    if (bc == M1O_PERIODIC) return ((t % n) + n) % n;
+    if (bc == M1O_REFLECT) return t < 0 ? -1 - t : 2 * n - 1 - t;
     return t < 0 ? 0 : n - 1;
 }
 
+/* State (E, Fx, Fy, Fz) of cell c whose index along d is t (possibly a
+ * ghost): a reflective ghost is the mirror cell with its F component normal
+ * to the boundary reversed; a fixed ghost carries the side's given state. */
+static void ghost_state(const m1o_problem *p, const double *const st[9], int d, const int c[3], int t,
+                        double q[4])
+{
+    int n = p->n[d];
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[d] = src_index(p, d, t);
+    long id = ((long)cc[2] * p->n[1] + cc[1]) * p->n[0] + cc[0];
+    for (int v = 0; v < 4; ++v) q[v] = st[v][id];
+    if (t >= 0 && t < n) return;
+    int side = t < 0 ? 0 : 1, bc = p->bc[d][side];
+    if (bc == M1O_REFLECT) q[1 + d] = -q[1 + d];
+    if (bc == M1O_FIXED)
+        for (int v = 0; v < 4; ++v) q[v] = p->bc_state[d][side][v];
+}
+
 /* Lower / upper face and centre coordinate of (possibly ghost) index t along d.
- * Periodic ghosts are shifted copies; outflow ghosts repeat the edge width. */
+ * Periodic ghosts are shifted copies, reflective ghosts mirror images of the
+ * interior cells; outflow and fixed ghosts repeat the edge width. */
 static void coords(const m1o_problem *p, int d, int t, double *lo, double *c, double *hi)
 {
     int n = p->n[d];
     const double *x = p->faces[d];
-    if (t >= 0 && t < n) {
+    int bc = (t >= 0 && t < n) ? -1 : p->bc[d][t < 0 ? 0 : 1];
+    if (bc < 0) {
         *lo = x[t]; *hi = x[t + 1];
-    } else if (p->bc[d][t < 0 ? 0 : 1] == M1O_PERIODIC) {
+    } else if (bc == M1O_PERIODIC) {
         int w = src_index(p, d, t);
         double shift = (double)((t - w) / n) * (x[n] - x[0]);
         *lo = x[w] + shift; *hi = x[w + 1] + shift;
+    } else if (bc == M1O_REFLECT) {
+        int m = src_index(p, d, t);
+        double wall = t < 0 ? x[0] : x[n];
+        *lo = 2.0 * wall - x[m + 1]; *hi = 2.0 * wall - x[m];
     } else if (t < 0) {
         double h = x[1] - x[0];
         *lo = x[0] + t * h; *hi = *lo + h;
@@ -136,9 +164,7 @@ static void face_state(const m1o_problem *p, const double *const st[9], int d, i
     int c[3] = {cbase[0], cbase[1], cbase[2]};
     double q[3][4], xc[3], lo, hi, xm;
     for (int s = -1; s <= 1; ++s) {
-        c[d] = src_index(p, d, t + s);
-        long id = lin(p, c);
-        for (int v = 0; v < 4; ++v) q[s + 1][v] = st[v][id];
+        ghost_state(p, st, d, c, t + s, q[s + 1]);
         coords(p, d, t + s, &lo, &xc[s + 1], &hi);
     }
     coords(p, d, t, &lo, &xm, &hi);

@@ -1,9 +1,9 @@
 // implicit.hip -- implicit radiation-matter step and the opacity cache.
 //
-// Per cell (Sect. 2.8): T^n from the gas energy, the 2x2 backward-Euler
+// Per cell (Sect. 2.7): T^n from the gas energy, the 2x2 backward-Euler
 // system of Eq. implicit_matrix solved analytically in FP64, flux damping of
 // Eq. source_discrete2, the gas total energy and momentum from the rescaled
-// conservation laws (Sect. 2.7), f <= 1, and the opacity cache (rho kappa_P,
+// conservation laws (Sect. 2.6), f <= 1, and the opacity cache (rho kappa_P,
 // optical depth rho chi h_max) re-evaluated at the new temperature for the
 // next transport and implicit steps.
 #include "m1_internal.h"

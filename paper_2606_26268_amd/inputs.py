@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 CARTESIAN, CYLINDRICAL, SPHERICAL = 0, 1, 2
-PERIODIC, OUTFLOW = 0, 1
+PERIODIC, OUTFLOW, REFLECT, FIXED = 0, 1, 2, 3
 OPAC_CONSTANT, OPAC_POWERLAW, OPAC_TABLE, OPAC_MLP = 0, 1, 2, 3
 
 FIELD_NAMES = ("E", "Fx", "Fy", "Fz", "rho", "mx", "my", "mz", "Eg")
@@ -55,6 +55,9 @@ class Problem:
     steps: int = 1
     recon: int = 0      # 0 f-preserving, 1 PLUTO flat, 2 simple clip
     riemann: int = 0    # 0 HLL, 1 Lax-Friedrichs-Rusanov
+    bc_state: list = None   # [[lo, hi]] * 3 ghost (E, Fx, Fy, Fz) of FIXED sides
+    irr: object = None      # per-cell irradiation heating -div F_irr (float64), or None
+    absorb_only: int = 0    # 1: absorption without emission
 
     @property
     def shape(self):
@@ -349,6 +352,38 @@ def make_beam(N=300, steps=None, cfl=0.4):
                    c_hat=1.0, c=1.0,
                    opacity=dict(kind=OPAC_CONSTANT, kP=0.0, kR=0.0, sigma=0.0),
                    fields=f, dt=dt, steps=steps)
+
+
+def make_shadow(nx=140, ny=40, absorb_only=1, t_end=2.0, cfl=0.4, a_rad=1e-12):
+    """Shadow test of Sect. 3.3 in code units (length in cm, c = c_hat = 1):
+    a 1 x 0.3 box (x in [-0.5, 0.5], y in [0, 0.3]), a free-streaming beam
+    injected at x = -0.5 (fixed ghost state, T_r / T = 6, F_x = E), outflow at
+    x = 0.5 and y = 0.3, reflective at y = 0; a spheroid of density 1000 in a
+    background of density 1, rho = 1 + 999 / (1 + e^D),
+    D = 10 [(x / 0.1)^2 + (y / 0.06)^2 - 1]; T = 1 everywhere, F = v = 0;
+    kappa_P = kappa_R = 0.1 rho T^-3.5 (Kramers).  The radiation constant is
+    small (a = 1e-12) so that, as in the paper's physical units, the gas heat
+    capacity dwarfs the radiation energy and T stays put."""
+    n = (nx, ny, 1)
+    faces = [uniform_faces(nx, -0.5, 0.5), uniform_faces(ny, 0.0, 0.3), np.array([0.0, 1.0])]
+    xc = 0.5 * (faces[0][1:] + faces[0][:-1])
+    yc = 0.5 * (faces[1][1:] + faces[1][:-1])
+    Y, X = np.meshgrid(yc, xc, indexing="ij")
+    D = 10.0 * ((X / 0.1) ** 2 + (Y / 0.06) ** 2 - 1.0)
+    rho = 1.0 + 999.0 / (1.0 + np.exp(D))
+    f = _zeros((1, ny, nx))
+    f["rho"][0] = rho
+    f["E"][:] = a_rad
+    gamma = 5.0 / 3.0
+    f["Eg"][0] = rho * 1.0 / (gamma - 1)
+    Eb = a_rad * 6.0 ** 4
+    dt = cfl / (1.0 / (faces[0][1] - faces[0][0]) + 1.0 / (faces[1][1] - faces[1][0]))
+    p = Problem("shadow", CARTESIAN, 2, n, faces, [[FIXED, OUTFLOW], [REFLECT, OUTFLOW], [PERIODIC, PERIODIC]],
+                c_hat=1.0, c=1.0, a_rad=a_rad, gamma=gamma,
+                opacity=dict(kind=OPAC_POWERLAW, k0=0.1, rho0=1.0, alpha=1.0, T0=1.0, beta=-3.5, sigma=0.0),
+                fields=f, dt=dt, steps=int(round(t_end / dt)),
+                bc_state=[[(Eb, Eb, 0.0, 0.0), None], [None, None], [None, None]], absorb_only=absorb_only)
+    return p
 
 
 def make_uniform(geometry, n, ndim, E=1.0, F=(0.0, 0.0, 0.0), bc=PERIODIC,
