@@ -53,7 +53,12 @@ typedef enum {
 } m1_status;
 
 typedef enum { M1_CARTESIAN = 0, M1_CYLINDRICAL = 1, M1_SPHERICAL = 2 } m1_geometry;
-typedef enum { M1_BC_PERIODIC = 0, M1_BC_OUTFLOW = 1 } m1_bc;
+/* boundaries: periodic wrap (paired), outflow (zero-gradient copy of the
+ * edge cell), reflective (mirror image of the interior with the flux
+ * component normal to the boundary reversed: the wall of the shadow test,
+ * Sect. 3.3) and fixed (a ghost state given by m1_set_boundary_state, e.g.
+ * a beam injected through the boundary, Sect. 3.3) */
+typedef enum { M1_BC_PERIODIC = 0, M1_BC_OUTFLOW = 1, M1_BC_REFLECT = 2, M1_BC_FIXED = 3 } m1_bc;
 typedef enum { M1_P64 = 0, M1_F32 = 1 } m1_precision;
 typedef enum { M1_OPAC_CONSTANT = 0, M1_OPAC_POWERLAW = 1 } m1_opacity_model;
 /* face treatment after reconstruction (Sect. 2.5; compared in Sect. 3.2) */
@@ -83,7 +88,11 @@ typedef struct {
  *         M1_RECON_PLUTO (flat face state whenever |R(F)| > R(E)) or
  *         M1_RECON_CLIP (F_f = R(F) R(E)/|R(F)| whenever |R(F)| > R(E))
  * riemann M1_RIEMANN_HLL (default) or M1_RIEMANN_LF (Lax-Friedrichs-Rusanov
- *         with the largest limited signal speed) */
+ *         with the largest limited signal speed)
+ * absorb_only  0 (default): the full radiation-matter system of
+ *         Eq. implicit_matrix; 1: absorption without emission,
+ *         E' = E* / (1 + dt c_hat kappa_P rho) (shadow test, Sect. 3.3), the
+ *         absorbed energy going to the gas */
 typedef struct {
     double c;
     double a_rad;
@@ -92,6 +101,7 @@ typedef struct {
     double e_floor;
     int recon;
     int riemann;
+    int absorb_only;
 } m1_params;
 
 /* Caller-owned device state bound to a context (see conventions). */
@@ -233,6 +243,22 @@ m1_status m1_step_explicit(m1_ctx *ctx, double dt);
  * temperature.  Asynchronous.  M1_ESTATE unless the previous step call was
  * m1_step_explicit. */
 m1_status m1_step_implicit(m1_ctx *ctx, double dt);
+
+/* Ghost state of a M1_BC_FIXED side: dir 0..2, side 0 (lower) or 1 (upper),
+ * state = (E, Fx, Fy, Fz) in the grid's local basis (host memory, copied),
+ * E > 0 and |F| <= E.  Every fixed side needs its state before the first
+ * m1_step_explicit (M1_ESTATE otherwise).  The optical depth of a fixed
+ * ghost is that of the adjacent interior cell.  M1_EINVAL for a side that
+ * is not fixed or an invalid state. */
+m1_status m1_set_boundary_state(m1_ctx *ctx, int dir, int side, const double state[4]);
+
+/* Irradiation heating (Sect. 2.8): q = -div F_irr per cell (device FP64,
+ * n0 n1 n2 values in the state layout, caller-owned, must stay valid while
+ * set), energy per unit volume and time.  Each implicit step deposits q dt:
+ * it enters the S_1 row of Eq. implicit_matrix and the conserved total
+ * E_g + (c/c_hat) E.  NULL switches irradiation off.  The caller updates
+ * the array between steps as the paper's user function does. */
+m1_status m1_set_irradiation(m1_ctx *ctx, const double *q);
 
 /* Second-order Runge-Kutta step of length dt built from the split step as in
  * Sect. 2.4 (every sub-step is transport then sources): U1 = S(T(U^n)),

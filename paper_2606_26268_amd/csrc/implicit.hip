@@ -25,6 +25,8 @@ struct IArgs {
     Metric<R> m;
     OpacityParams op;
     ImplicitConsts k;
+    const double *irr;                // irradiation heating per cell, or null
+    int absorb;                       // absorption without emission
     unsigned long long *cnt;
 };
 
@@ -87,7 +89,9 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     const double g = a.k.dt_c * rkP;
     const double aT3 = a.k.a * T * T * T, aT4 = aT3 * T;
     const double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
-    double E1 = (Cv * (Es + gr * aT4) + 4.0 * g * aT3 * Es) / det;
+    // irradiation energy deposited in the step enters the S_1 row (Sect. 2.8)
+    const double S = a.irr ? a.irr[id] * a.k.dt : 0.0;
+    double E1 = a.absorb ? Es / (1.0 + gr) : (Cv * (Es + gr * aT4) + 4.0 * aT3 * (g * Es + gr * S)) / det;
     const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rchi);   // Eq. source_discrete2
     double F1[3] = {Fs[0] * inv_damp, Fs[1] * inv_damp, Fs[2] * inv_damp};
     const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
@@ -101,7 +105,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     // stored (possibly float) values define the exchanged amounts, so the
     // rescaled totals E_g + (c/c_hat) E and m + F/c_hat are conserved
     const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
-    Eg -= a.k.c_ratio * (double(E1r) - Es);
+    Eg += S - a.k.c_ratio * (double(E1r) - Es);
     mx -= (double(F1r[0]) - Fs[0]) * a.k.inv_ch;
     my -= (double(F1r[1]) - Fs[1]) * a.k.inv_ch;
     mz -= (double(F1r[2]) - Fs[2]) * a.k.inv_ch;
@@ -196,6 +200,8 @@ static void fill_args(m1_ctx *c, IArgs<R> &a, const Metric<R> &met, double dt)
     a.k.dt_c = dt * c->par.c;
     a.k.inv_ch = 1.0 / c->c_hat;
     a.k.c_ratio = c->par.c * a.k.inv_ch;
+    a.irr = c->irr;
+    a.absorb = c->par.absorb_only;
     a.cnt = c->cnt;
 }
 

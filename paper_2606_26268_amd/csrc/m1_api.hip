@@ -55,6 +55,12 @@ static void ghost_coords(const m1_ctx *c, int d, int t, double &lo, double &ce, 
         const double L = x[n] - x[0];
         lo = x[w] + shift * L;
         hi = x[w + 1] + shift * L;
+    } else if (c->bc[d][t < 0 ? 0 : 1] == M1_BC_REFLECT) {
+        // mirror image of the interior cell across the wall
+        const int m = t < 0 ? -1 - t : 2 * n - 1 - t;
+        const double wall = t < 0 ? x[0] : x[n];
+        lo = 2.0 * wall - x[m + 1];
+        hi = 2.0 * wall - x[m];
     } else if (t < 0) {
         const double h = x[1] - x[0];
         lo = x[0] + t * h;
@@ -235,6 +241,7 @@ m1_status m1_params_default(double c_hat, m1_params *p)
     p->e_floor = 1e-30;
     p->recon = M1_RECON_FPRESERVE;
     p->riemann = M1_RIEMANN_HLL;
+    p->absorb_only = 0;
     return M1_OK;
 }
 
@@ -251,10 +258,12 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
         if (d >= g->ndim && g->n[d] != 1) return fail(M1_EINVAL, "m1_create: n[d] must be 1 for inactive d");
         if (!g->faces[d]) return fail(M1_EINVAL, "m1_create: NULL faces");
         for (int s = 0; s < 2; ++s)
-            if (g->bc[d][s] != M1_BC_PERIODIC && g->bc[d][s] != M1_BC_OUTFLOW)
+            if (g->bc[d][s] < M1_BC_PERIODIC || g->bc[d][s] > M1_BC_FIXED)
                 return fail(M1_EINVAL, "m1_create: unknown boundary condition");
         if ((g->bc[d][0] == M1_BC_PERIODIC) != (g->bc[d][1] == M1_BC_PERIODIC))
             return fail(M1_EINVAL, "m1_create: periodic boundaries must be paired");
+        if (d < g->ndim && g->n[d] < 2 && (g->bc[d][0] == M1_BC_REFLECT || g->bc[d][1] == M1_BC_REFLECT))
+            return fail(M1_EINVAL, "m1_create: a reflective direction needs at least 2 cells");
         for (int t = 0; t < g->n[d]; ++t)
             if (!(g->faces[d][t + 1] > g->faces[d][t]))
                 return fail(M1_EINVAL, "m1_create: faces must be strictly increasing");
@@ -273,6 +282,8 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
     if (par.recon < M1_RECON_FPRESERVE || par.recon > M1_RECON_CLIP || par.riemann < M1_RIEMANN_HLL ||
         par.riemann > M1_RIEMANN_LF)
         return fail(M1_EINVAL, "m1_create: unknown reconstruction or Riemann solver");
+    if (par.absorb_only != 0 && par.absorb_only != 1)
+        return fail(M1_EINVAL, "m1_create: absorb_only must be 0 or 1");
     if (!(par.c > 0.0) || !(par.gamma > 1.0) || !(par.a_rad > 0.0))
         return fail(M1_EINVAL, "m1_create: c, a_rad must be > 0 and gamma > 1");
     m1_ctx *c = new (std::nothrow) m1_ctx();
@@ -490,11 +501,45 @@ m1_status m1_max_dt(const m1_ctx *c, double cfl, double *dt)
     return M1_OK;
 }
 
+// every fixed side has its ghost state
+static bool fixed_states_ready(const m1_ctx *c)
+{
+    for (int d = 0; d < c->ndim; ++d)
+        for (int s = 0; s < 2; ++s)
+            if (c->bc[d][s] == M1_BC_FIXED && !c->bc_state_set[d][s]) return false;
+    return true;
+}
+
+m1_status m1_set_boundary_state(m1_ctx *c, int dir, int side, const double state[4])
+{
+    if (!c || !state) return fail(M1_EINVAL, "m1_set_boundary_state: NULL argument");
+    if (dir < 0 || dir > 2 || side < 0 || side > 1)
+        return fail(M1_EINVAL, "m1_set_boundary_state: dir must be 0..2 and side 0 or 1");
+    if (c->bc[dir][side] != M1_BC_FIXED)
+        return fail(M1_EINVAL, "m1_set_boundary_state: that side is not a fixed boundary");
+    const double F2 = state[1] * state[1] + state[2] * state[2] + state[3] * state[3];
+    if (!(state[0] > 0) || !std::isfinite(state[0]) || !(F2 <= state[0] * state[0]))
+        return fail(M1_EINVAL, "m1_set_boundary_state: need E > 0 and |F| <= E");
+    for (int v = 0; v < 4; ++v) c->bc_state[dir][side][v] = state[v];
+    c->bc_state_set[dir][side] = true;
+    return M1_OK;
+}
+
+m1_status m1_set_irradiation(m1_ctx *c, const double *q)
+{
+    if (!c) return fail(M1_EINVAL, "m1_set_irradiation: NULL context");
+    if (q && reinterpret_cast<uintptr_t>(q) % alignof(double))
+        return fail(M1_EINVAL, "m1_set_irradiation: misaligned array");
+    c->irr = q;
+    return M1_OK;
+}
+
 m1_status m1_step_explicit(m1_ctx *c, double dt)
 {
     if (!c) return fail(M1_EINVAL, "m1_step_explicit: NULL context");
     if (!c->bound) return fail(M1_ESTATE, "m1_step_explicit: no state bound");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(M1_EINVAL, "m1_step_explicit: dt must be > 0");
+    if (!fixed_states_ready(c)) return fail(M1_ESTATE, "m1_step_explicit: a fixed boundary has no state");
     hipError_t e = launch_transport(c, dt);
     if (e != hipSuccess) return hip_fail(e, "m1_step_explicit launch");
     c->transported = true;
@@ -518,6 +563,7 @@ m1_status m1_step_rk2(m1_ctx *c, double dt)
     if (!c) return fail(M1_EINVAL, "m1_step_rk2: NULL context");
     if (!c->bound) return fail(M1_ESTATE, "m1_step_rk2: no state bound");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(M1_EINVAL, "m1_step_rk2: dt must be > 0");
+    if (!fixed_states_ready(c)) return fail(M1_ESTATE, "m1_step_rk2: a fixed boundary has no state");
     const long N = ncells(c);
     const size_t per = ((N * elem_size(c) + 255) / 256) * 256;
     if (!c->rk2_save) {

@@ -66,6 +66,9 @@ struct m1_ctx {
     m1::Metric<float> met32{};
     double *vol_dev[3] = {nullptr, nullptr, nullptr};  // volume factors (double)
     int ign[3] = {0, 0, 0};   // inactive direction with unequal face areas
+    double bc_state[3][2][4] = {};         // ghost state of fixed sides
+    bool bc_state_set[3][2] = {};
+    const double *irr = nullptr;           // irradiation heating per cell (caller's)
 
     // bound state
     bool bound = false;

@@ -22,21 +22,47 @@ struct TArgs {
     Metric<R> m;
     R dt, c_hat, e_floor;
     int recon, riemann;
+    int special;               // some side is reflective or fixed
+    R bcs[3][2][4];            // ghost state of fixed sides
     unsigned long long *cnt;
 };
 
-// index along one direction after applying the boundary condition
+// index along one direction after applying the boundary condition: periodic
+// wrap, mirror image (reflective), or the edge cell (outflow and fixed,
+// whose ghost state is replaced by ghost_fix).  Mirror indices past the
+// interior (cells no face uses, in ragged tiles) are clamped.
 __device__ __forceinline__ int map_index(int t, int n, int lo, int hi)
 {
     if (t < 0) {
         if (lo == M1_BC_PERIODIC) { while (t < 0) t += n; return t; }
+        if (lo == M1_BC_REFLECT) return min(-1 - t, n - 1);
         return 0;
     }
     if (t >= n) {
         if (hi == M1_BC_PERIODIC) { while (t >= n) t -= n; return t; }
+        if (hi == M1_BC_REFLECT) return max(2 * n - 1 - t, 0);
         return n - 1;
     }
     return t;
+}
+
+// State of a ghost cell of direction d at index t (t outside [0, n)): a
+// reflective side reverses the flux component normal to it, a fixed side
+// supplies its given state.  Interior indices are left alone.
+template <typename R>
+__device__ __forceinline__ void ghost_fix(const TArgs<R> &a, int d, int t, int n, R q[4])
+{
+    if (t >= 0 && t < n) return;
+    const int side = t < 0 ? 0 : 1;
+    const int bc = a.bc[d][side];
+    if (bc == M1_BC_REFLECT) {
+        if (d == 0) q[1] = -q[1];
+        else if (d == 1) q[2] = -q[2];
+        else q[3] = -q[3];
+    } else if (bc == M1_BC_FIXED) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[v] = a.bcs[d][side][v];
+    }
 }
 
 template <typename R>
@@ -63,6 +89,7 @@ __device__ __forceinline__ void direction_div(const TArgs<R> &a, int base, int s
     for (int s = 0; s < 5; ++s) {
         li[s] = base + map_index(t - 2 + s, n, lo, hi) * stride;
         load4(a, li[s], q[s]);
+        if (a.special) ghost_fix(a, D, t - 2 + s, n, q[s]);
     }
     const R *winv = a.m.winv[D], *hp = a.m.hp[D], *hm = a.m.hm[D];
     // face states: cell t-1 upper, cell t lower and upper, cell t+1 lower
@@ -250,6 +277,19 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         const int gj = map_index(y0 - 2 + hy, n1, a.bc[1][0], a.bc[1][1]);
         hcol = gj * n0 + gi;
     }
+    // ghost transformation of a state in this thread's column (x, y ghosts)
+    // and in plane kk (z ghosts); halo cells are ghosts in x or y only
+    auto fix_col = [&](int kk, R q[4]) {
+        if (!a.special) return;
+        ghost_fix(a, 0, i, n0, q);
+        ghost_fix(a, 1, j, n1, q);
+        ghost_fix(a, 2, kk, n2, q);
+    };
+    auto fix_halo = [&](R q[4]) {
+        if (!a.special) return;
+        ghost_fix(a, 0, x0 - 2 + hx, n0, q);
+        ghost_fix(a, 1, y0 - 2 + hy, n1, q);
+    };
 
     // slope tasks: centre cell in sq (flat), neighbour stride, inverse spacings.
     // Cells past the last ghost (m > n) feed no face and are skipped.
@@ -343,6 +383,11 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         load4(a, zlin(z0, col), W[1]);
         load4(a, zlin(z0 + 1, col), W[2]);
         load4(a, zlin(z0 + 2, col), W[3]);
+        fix_col(z0 - 2, Q0);
+        fix_col(z0 - 1, W[0]);
+        fix_col(z0, W[1]);
+        fix_col(z0 + 1, W[2]);
+        fix_col(z0 + 2, W[3]);
         const R Tm = a.tau[zlin(z0 - 1, col)];
         T1 = a.tau[zlin(z0, col)];
         T2 = a.tau[zlin(z0 + 1, col)];
@@ -355,10 +400,12 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         // prefetch the plane entering the window and this plane's halo
         R Qn[4];
         load4(a, zlin(k + 3, col), Qn);
+        fix_col(k + 3, Qn);
         const R Tn = a.tau[zlin(k + 2, col)];
         R Hq[4], Ht = R(0);
         if (tid < NHALO) {
             load4(a, k * plane + hcol, Hq);
+            fix_halo(Hq);
             Ht = a.tau[k * plane + hcol];
         }
 #pragma unroll
@@ -460,6 +507,12 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
     a.e_floor = R(c->par.e_floor);
     a.recon = c->par.recon;
     a.riemann = c->par.riemann;
+    a.special = 0;
+    for (int d = 0; d < 3; ++d)
+        for (int sd = 0; sd < 2; ++sd) {
+            if (c->bc[d][sd] == M1_BC_REFLECT || c->bc[d][sd] == M1_BC_FIXED) a.special = 1;
+            for (int v = 0; v < 4; ++v) a.bcs[d][sd][v] = R(c->bc_state[d][sd][v]);
+        }
     a.cnt = c->cnt;
     const int N = c->n[0] * c->n[1] * c->n[2];
     if (c->ndim == 3) {

@@ -42,7 +42,8 @@ class m1_grid(C.Structure):
 
 class m1_params(C.Structure):
     _fields_ = [("c", C.c_double), ("a_rad", C.c_double), ("gamma", C.c_double),
-                ("precision", C.c_int), ("e_floor", C.c_double), ("recon", C.c_int), ("riemann", C.c_int)]
+                ("precision", C.c_int), ("e_floor", C.c_double), ("recon", C.c_int), ("riemann", C.c_int),
+                ("absorb_only", C.c_int)]
 
 
 class m1_fields(C.Structure):
@@ -76,7 +77,8 @@ class m1_train_report(C.Structure):
 EXPORTS = ("m1_params_default", "m1_create", "m1_destroy", "m1_set_stream", "m1_bind_state",
            "m1_set_opacity_model", "m1_set_opacity_table", "m1_set_opacity_mlp", "m1_mlp_train",
            "m1_mlp_get", "m1_mlp_gradient", "m1_opacity_eval", "m1_max_dt", "m1_step_explicit", "m1_step_implicit", "m1_step_rk2",
-           "m1_transported", "m1_refresh_opacity", "m1_sync", "m1_diagnostics", "m1_last_error")
+           "m1_transported", "m1_refresh_opacity", "m1_sync", "m1_diagnostics", "m1_last_error",
+           "m1_set_boundary_state", "m1_set_irradiation")
 
 _lib = None
 
@@ -110,6 +112,8 @@ def lib():
             "m1_refresh_opacity": [vp],
             "m1_sync": [vp],
             "m1_diagnostics": [vp, C.POINTER(m1_diag)],
+            "m1_set_boundary_state": [vp, C.c_int, C.c_int, dp],
+            "m1_set_irradiation": [vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -242,6 +246,17 @@ def m1_max_dt(ctx, cfl):
     return dt.value
 
 
+def m1_set_boundary_state(ctx, direction, side, state):
+    st = (C.c_double * 4)(*[float(v) for v in state])
+    _check(lib().m1_set_boundary_state(ctx, int(direction), int(side), st))
+
+
+def m1_set_irradiation(ctx, q):
+    """q: CUDA float64 tensor of the cell count (or None to switch off); the
+    caller keeps it alive while it is set."""
+    _check(lib().m1_set_irradiation(ctx, None if q is None else q.data_ptr()))
+
+
 def m1_step_explicit(ctx, dt):
     _check(lib().m1_step_explicit(ctx, float(dt)))
 
@@ -304,7 +319,19 @@ class Solver:
         par.c, par.a_rad, par.gamma = prob.c, prob.a_rad, prob.gamma
         par.precision, par.e_floor = self.precision, prob.e_floor
         par.recon, par.riemann = getattr(prob, "recon", 0), getattr(prob, "riemann", 0)
+        par.absorb_only = int(getattr(prob, "absorb_only", 0))
         self.ctx = m1_create(prob.ndim, prob.n, prob.faces, prob.bc, prob.geometry, prob.c_hat, par)
+        bs = getattr(prob, "bc_state", None)
+        if bs is not None:
+            for d in range(3):
+                for side in range(2):
+                    if bs[d][side] is not None:
+                        m1_set_boundary_state(self.ctx, d, side, bs[d][side])
+        irr = getattr(prob, "irr", None)
+        self.irr = None
+        if irr is not None:
+            self.irr = torch.from_numpy(np.ascontiguousarray(irr, dtype=np.float64)).to(self.device).contiguous()
+            m1_set_irradiation(self.ctx, self.irr)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         m1_set_stream(self.ctx, self.stream.cuda_stream)
         op = prob.opacity
