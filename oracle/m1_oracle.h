@@ -84,6 +84,15 @@ int m1o_run(const m1o_problem *p, double dt, int nsteps, double *const st[9],
 int m1o_run_rk2(const m1o_problem *p, double dt, int nsteps, double *const st[9],
                 long long cnt[M1O_NCNT]);
 
+/* --- multigroup (one gray fluid per group, (m+1)^2 implicit system) ------- */
+#define M1O_MAX_GROUPS 32
+double m1o_planck_cdf(double x);
+void m1o_group_fractions(int m, const double *edges, double T, double *b);
+int m1o_mg_cell(int m, const double *Es, double Cv, double T, const double *kP, double rho, double dt,
+                double c_hat, double c, double a, const double *b, double S, double *out);
+int m1o_run_mg(const m1o_problem *p, int m, const double *edges, const double *kPg, const double *kRg,
+               double dt, int nsteps, double *const rad[], double *const gas[5], long long cnt[M1O_NCNT]);
+
 /* --- single-cell implicit solve (both algebraic forms) -------------------- */
 void m1o_implicit_cell(double Es, double Cv, double T, double kP, double rho, double dt,
                        double c_hat, double c, double a, double S, double out[4]);

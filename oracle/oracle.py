@@ -13,7 +13,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["closure.c", "transport.c", "implicit.c", "mlp.c"]
+SOURCES = ["closure.c", "transport.c", "implicit.c", "mlp.c", "multigroup.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 NCNT = 4
@@ -102,6 +102,13 @@ def lib():
         L.m1o_mlp_loss_grad.restype = C.c_double
         L.m1o_mlp_loss_grad.argtypes = [_dp, C.c_int, C.c_long, _dp, _dp, _dp]
         L.m1o_adam.argtypes = [C.c_long, _dp, _dp, _dp, _dp, C.c_long] + [C.c_double] * 4
+        L.m1o_planck_cdf.restype = C.c_double
+        L.m1o_planck_cdf.argtypes = [C.c_double]
+        L.m1o_group_fractions.argtypes = [C.c_int, _dp, C.c_double, _dp]
+        L.m1o_mg_cell.restype = C.c_int
+        L.m1o_mg_cell.argtypes = [C.c_int, _dp] + [C.c_double] * 2 + [_dp] + [C.c_double] * 5 + [_dp, C.c_double, _dp]
+        L.m1o_run_mg.restype = C.c_int
+        L.m1o_run_mg.argtypes = [C.POINTER(Problem), C.c_int, _dp, _dp, _dp, C.c_double, C.c_int, pp, pp, cnt]
         L.m1o_bf16_round.restype = C.c_double
         L.m1o_bf16_round.argtypes = [C.c_double]
         _lib = L
@@ -204,6 +211,30 @@ class Oracle:
         rc = fn(C.byref(self.P), dt, int(nsteps), self._pp(arrs), cnt)
         if rc != 0:
             raise MemoryError("oracle run failed")
+        return st, np.array(list(cnt))
+
+    def run_mg(self, fields, dt, nsteps):
+        """Multigroup run (prob.groups = dict(edges, kP, kR)): fields E, Fx,
+        Fy, Fz have a leading group axis; returns (fields, counters)."""
+        gr = self.prob.groups
+        m = len(gr["kP"])
+        edges = np.ascontiguousarray(gr["edges"], dtype=np.float64).reshape(-1)
+        assert edges.size == m - 1
+        kP = np.ascontiguousarray(gr["kP"], dtype=np.float64)
+        kR = np.ascontiguousarray(gr["kR"], dtype=np.float64)
+        st = {k: np.ascontiguousarray(v, dtype=np.float64).copy() for k, v in fields.items()}
+        rad = []
+        for g in range(m):
+            for k in ("E", "Fx", "Fy", "Fz"):
+                a = st[k][g]
+                assert a.flags.c_contiguous and a.size == self.N
+                rad.append(a)
+        gas = self._arrs(st, ("rho", "mx", "my", "mz", "Eg"))
+        cnt = (C.c_longlong * NCNT)()
+        rc = lib().m1o_run_mg(C.byref(self.P), m, _ptr(edges), _ptr(kP), _ptr(kR), dt, int(nsteps),
+                              self._pp(rad), self._pp(gas), cnt)
+        if rc != 0:
+            raise RuntimeError("oracle multigroup run failed")
         return st, np.array(list(cnt))
 
     def explicit(self, fields, dt):
@@ -353,3 +384,26 @@ def adam(theta, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 def bf16_round(x):
     return lib().m1o_bf16_round(float(x))
+
+
+def planck_cdf(x):
+    return lib().m1o_planck_cdf(float(x))
+
+
+def group_fractions(edges, T):
+    edges = np.ascontiguousarray(edges, dtype=np.float64).reshape(-1)
+    b = np.zeros(edges.size + 1)
+    lib().m1o_group_fractions(edges.size + 1, _ptr(edges), float(T), _ptr(b))
+    return b
+
+
+def mg_cell(Es, Cv, T, kP, rho, dt, c_hat, c, a, b, S=0.0):
+    Es = np.ascontiguousarray(Es, dtype=np.float64)
+    kP = np.ascontiguousarray(kP, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    out = np.zeros(Es.size + 1)
+    rc = lib().m1o_mg_cell(Es.size, _ptr(Es), float(Cv), float(T), _ptr(kP), float(rho), float(dt),
+                           float(c_hat), float(c), float(a), _ptr(b), float(S), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("singular multigroup system")
+    return out

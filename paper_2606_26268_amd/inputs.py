@@ -58,6 +58,7 @@ class Problem:
     bc_state: list = None   # [[lo, hi]] * 3 ghost (E, Fx, Fy, Fz) of FIXED sides
     irr: object = None      # per-cell irradiation heating -div F_irr (float64), or None
     absorb_only: int = 0    # 1: absorption without emission
+    groups: dict = None     # multigroup: dict(edges=[m-1], kP=[m], kR=[m]); E, F get a leading group axis
 
     @property
     def shape(self):
