@@ -219,6 +219,9 @@ def main():
                                ("c2_p64_const", I.make_c2, "p64"), ("c2_f32_const", I.make_c2, "f32")):
             log(f"form {name}")
             forms[name] = time_form(m1, torch, mk(), prec, K, W)
+        for name, prec in (("c1_mg8_f32", "f32"), ("c1_mg8_p64", "p64")):
+            log(f"form {name}")
+            forms[name] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), prec, K, W)
 
     ncell = 192 * 96 * 192
     # both kernels of the headline form are bound by vector-ALU issue (the
@@ -243,8 +246,12 @@ def main():
     out_forms = {}
     for name, r in forms.items():
         prec = "f32" if "f32" in name else "p64"
-        kind = "const" if "const" in name else "table"
+        kind = "const" if ("const" in name or "mg" in name) else "table"
         bps = algorithmic_bytes("transport", prec, kind) + algorithmic_bytes("implicit", prec, kind)
+        if "_mg8_" in name:
+            # per group: transport (E, F, tau in; E*, F* out) and E*, F* in / E, F out; gas once
+            s = 4 if prec == "f32" else 8
+            bps = 8 * (9 * s + 8 * s) + 72
         out_forms[name] = dict(cells_per_s=r["cells_per_s"], ms_per_step=r["ms_per_step"],
                                transport_ms=r["transport_ms"], implicit_ms=r["implicit_ms"],
                                bytes_per_cell_step=bps,

@@ -244,6 +244,23 @@ m1_status m1_step_explicit(m1_ctx *ctx, double dt);
  * m1_step_explicit. */
 m1_status m1_step_implicit(m1_ctx *ctx, double dt);
 
+/* Multigroup M1 (Sect. 2.3, 2.7): m frequency groups, each transported as
+ * an independent gray M1 fluid, coupled to the gas by the (m+1)^2 implicit
+ * system in which group g emits the Planck fraction b_g(T^n) of a T^4
+ * (fraction of int B_nu over its band at the start-of-step temperature).
+ * edges: m-1 increasing interior group boundaries x_g = h nu_g / k, in the
+ * temperature unit (> 0; NULL for m = 1); kP, kR: m constant Planck and
+ * Rosseland opacities per group (>= 0); sigma: scattering (>= 0).  All host
+ * memory, copied.  Call before m1_bind_state; afterwards the bound E, Fx,
+ * Fy, Fz hold m n0 n1 n2 values each, group-major (group g starts at
+ * g n0 n1 n2).  The group opacities replace the gray opacity model.  m = 1
+ * returns to the gray model.  1 <= m <= M1_MAX_GROUPS.  M1_ESTATE once a
+ * state is bound; m1_step_rk2 and m1_opacity_eval return M1_ENOTSUP while
+ * m > 1. */
+#define M1_MAX_GROUPS 32
+m1_status m1_set_groups(m1_ctx *ctx, int m, const double *edges, const double *kP, const double *kR,
+                        double sigma);
+
 /* Ghost state of a M1_BC_FIXED side: dir 0..2, side 0 (lower) or 1 (upper),
  * state = (E, Fx, Fy, Fz) in the grid's local basis (host memory, copied),
  * E > 0 and |F| <= E.  Every fixed side needs its state before the first
@@ -269,7 +286,8 @@ m1_status m1_set_irradiation(m1_ctx *ctx, const double *q);
 m1_status m1_step_rk2(m1_ctx *ctx, double dt);
 
 /* Device pointers of the library's transported state E*, Fx*, Fy*, Fz*
- * (valid after m1_step_explicit; owned by the library). */
+ * (valid after m1_step_explicit; owned by the library).  Gray states only
+ * (M1_ENOTSUP with groups). */
 m1_status m1_transported(m1_ctx *ctx, void **E, void **Fx, void **Fy, void **Fz);
 
 /* Re-evaluate the opacity cache from the bound gas state (call after the

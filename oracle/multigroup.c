@@ -159,7 +159,8 @@ int m1o_run_mg(const m1o_problem *p, int m, const double *edges, const double *k
             if (m1o_mg_cell(m, Es, Cv, T, kPg, rho, dt, p->c_hat, p->c, p->a_rad, b, S, x)) { ++bad; continue; }
             double dE = 0.0, dF[3] = {0, 0, 0};
             for (int g = 0; g < m; ++g) {
-                double E1 = x[g];
+                /* absorption only (Sect. 3.3): no emission in any group */
+                double E1 = p->absorb_only ? Es[g] / (1.0 + dt * p->c_hat * kPg[g] * rho) : x[g];
                 double damp = 1.0 + dt * p->c_hat * (kRg[g] + p->sigma) * rho;
                 double F1[3], Fs[3];
                 for (int q = 0; q < 3; ++q) {

@@ -1,5 +1,6 @@
 // diag.hip -- deterministic reductions of the bound state: sum V E,
-// sum V (E_g + (c/c_hat) E), sum V (m + F / c_hat), min E, max f.
+// sum V (E_g + (c/c_hat) E), sum V (m + F / c_hat), min E, max f (E and F
+// summed over the frequency groups; min E and max f over every group).
 // Two passes with a fixed summation order (block partials, then one block),
 // so repeated calls on the same state give bit-identical results.
 #include "m1_internal.h"
@@ -15,6 +16,7 @@ struct DArgs {
     const double *mx, *my, *mz, *Eg;
     const double *vol[3];
     int n[3];
+    int groups;                // radiation arrays hold `groups` consecutive fields
     double ratio, inv_ch;
     double *partials;
 };
@@ -30,16 +32,24 @@ __global__ void __launch_bounds__(256) k_diag_partial(DArgs<R> a)
     for (int id = blockIdx.x * 256 + threadIdx.x; id < N; id += gridDim.x * 256) {
         const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
         const double V = a.vol[0][i] * a.vol[1][j] * a.vol[2][k];
-        const double E = double(a.E[id]);
-        const double Fx = double(a.Fx[id]), Fy = double(a.Fy[id]), Fz = double(a.Fz[id]);
-        acc[0] += V * E;
-        acc[1] += V * (a.Eg[id] + a.ratio * E);
-        acc[2] += V * (a.mx[id] + Fx * a.inv_ch);
-        acc[3] += V * (a.my[id] + Fy * a.inv_ch);
-        acc[4] += V * (a.mz[id] + Fz * a.inv_ch);
-        mn = E < mn ? E : mn;
-        const double f = sqrt(Fx * Fx + Fy * Fy + Fz * Fz) / E;
-        mx = f > mx ? f : mx;
+        double Et = 0.0, Ft[3] = {0.0, 0.0, 0.0};
+        for (int g = 0; g < a.groups; ++g) {
+            const long gid = long(g) * N + id;
+            const double E = double(a.E[gid]);
+            const double Fx = double(a.Fx[gid]), Fy = double(a.Fy[gid]), Fz = double(a.Fz[gid]);
+            Et += E;
+            Ft[0] += Fx;
+            Ft[1] += Fy;
+            Ft[2] += Fz;
+            mn = E < mn ? E : mn;
+            const double f = sqrt(Fx * Fx + Fy * Fy + Fz * Fz) / E;
+            mx = f > mx ? f : mx;
+        }
+        acc[0] += V * Et;
+        acc[1] += V * (a.Eg[id] + a.ratio * Et);
+        acc[2] += V * (a.mx[id] + Ft[0] * a.inv_ch);
+        acc[3] += V * (a.my[id] + Ft[1] * a.inv_ch);
+        acc[4] += V * (a.mz[id] + Ft[2] * a.inv_ch);
     }
     for (int v = 0; v < 5; ++v) sh[v][threadIdx.x] = acc[v];
     sh[5][threadIdx.x] = mn;
@@ -98,6 +108,7 @@ static hipError_t launch_d(m1_ctx *c, double out[8])
         a.vol[d] = c->vol_dev[d];
         a.n[d] = c->n[d];
     }
+    a.groups = c->grp.m;
     a.ratio = c->par.c / c->c_hat;
     a.inv_ch = 1.0 / c->c_hat;
     a.partials = c->partials;

@@ -223,8 +223,168 @@ static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// multigroup (one gray fluid per frequency group, (m+1)^2 implicit system)
+// ---------------------------------------------------------------------------
+
+// Fraction of the Planck energy density below x = h nu / k T,
+// (15 / pi^4) int_0^x t^3 / (e^t - 1) dt.  Below x = 1: the power series of
+// t^3 / (e^t - 1) integrated term by term (coefficients B_k / ((k + 3) k!),
+// B_k the Bernoulli numbers); above: 1 minus the tail
+// sum_n e^{-n x} (x^3/n + 3 x^2/n^2 + 6 x/n^3 + 6/n^4), summed until the
+// terms drop below double precision.
+__device__ double planck_fraction(double x)
+{
+    constexpr double NORM = 0.15398973382026503;   // 15 / pi^4
+    if (x <= 0.0) return 0.0;
+    if (x < 1.0) {
+        // B_k / ((k + 3) k!) for k = 0, 1, 2, 4, 6, ..., 18 (odd B_k > 1 vanish)
+        constexpr double C[11] = {
+            1.0 / 3.0, -1.0 / 8.0, 1.0 / 60.0, -1.0 / 5040.0, 1.0 / 272160.0, -1.0 / 13305600.0,
+            1.0 / 622702080.0, -691.0 / 19615115520000.0, 1.0 / 1270312243200.0,
+            -3617.0 / 202741834014720000.0, 43867.0 / 107290978560589824000.0};
+        const double x2 = x * x;
+        // x^3 (C0 + C1 x + x^2 (C2 + C3 x^2 + C4 x^4 + ...))
+        double p = C[10];
+        for (int j = 9; j >= 2; --j) p = p * x2 + C[j];
+        const double series = C[0] + x * C[1] + x2 * p;
+        return NORM * x * x2 * series;
+    }
+    const double e1 = exp(-x);
+    const double x2 = x * x, x3 = x2 * x;
+    double e = e1, tail = 0.0;
+    for (int n = 1; n <= 64 && e > 1e-18 * e1; ++n) {
+        const double rn = 1.0 / n;
+        tail += e * rn * (x3 + rn * (3.0 * x2 + rn * (6.0 * x + rn * 6.0)));
+        e *= e1;
+    }
+    return 1.0 - NORM * tail;
+}
+
+template <typename R>
+struct MgArgs {
+    GroupParams gp;
+    long N;
+    size_t plane;                     // bytes between scratch fields
+    const unsigned char *star;        // transported group states
+};
+
+// Optical depth of every group from the gas density (constant opacities).
+template <typename R>
+__global__ void __launch_bounds__(256) k_tau_mg(IArgs<R> a, MgArgs<R> g, unsigned char *tau)
+{
+    const int n0 = a.n[0], n1 = a.n[1];
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    const R h = cell_hmax(a.m, a.ndim, i, j, k);
+    const double rho = a.rho[id];
+    for (int q = 0; q < g.gp.m; ++q)
+        reinterpret_cast<R *>(tau + q * g.plane)[id] = R(rho * (g.gp.kR[q] + g.gp.sigma)) * h;
+}
+
+// One cell of the multigroup implicit step.  The (m+1)^2 system
+//   (1 + gr_g) E'_g - 4 gr_g b_g a T^3 T' = E*_g - 3 gr_g b_g a T^4
+//   -sum_g g_g E'_g + (C_v + 4 sum_g g_g b_g a T^3) T' = C_v T + 3 sum_g g_g b_g a T^4 + S
+// is an arrowhead matrix: eliminating the group rows leaves one equation
+// for T' whose coefficients are sums of positive terms,
+//   D  = C_v + sum_g 4 g_g b_g a T^3 / (1 + gr_g),
+//   L  = a (4 T^3 T' - 3 T^4) = a T^3 (C_v T + 4 S + 4 sum_g g_g E*_g / (1 + gr_g)) / D,
+//   E'_g = (E*_g + gr_g b_g L) / (1 + gr_g),
+// O(m) work and no cancellation.
+template <typename R>
+__global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
+{
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    const int m = g.gp.m;
+    const double rho = a.rho[id];
+    double mx = a.mx[id], my = a.my[id], mz = a.mz[id], Eg = a.Eg[id];
+    const double inv_rho = 1.0 / rho;
+    const double Cv = rho * a.k.inv_gm1;
+    const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
+    const double S = a.irr ? a.irr[id] * a.k.dt : 0.0;
+    const double aT3 = a.k.a * T * T * T;
+    const double iT = 1.0 / T;
+    auto Es_of = [&](int q) { return double(reinterpret_cast<const R *>(g.star + 4 * q * g.plane)[id]); };
+    // pass 1: the reduced equation for the temperature
+    double D = Cv, Lnum = Cv * T + 4.0 * S, lo = 0.0;
+    for (int q = 0; q < m; ++q) {
+        const double hi = q + 1 < m ? planck_fraction(g.gp.edges[q] * iT) : 1.0;
+        const double b = hi - lo;
+        lo = hi;
+        const double kr = rho * g.gp.kP[q];
+        const double inv1 = 1.0 / (1.0 + a.k.dt_ch * kr);
+        const double gg = a.k.dt_c * kr;
+        D += 4.0 * gg * b * aT3 * inv1;
+        Lnum += 4.0 * gg * Es_of(q) * inv1;
+    }
+    const double L = aT3 * Lnum / D;
+    // pass 2: group energies, damped fluxes, rescaled totals
+    double dE = 0.0, dF[3] = {0.0, 0.0, 0.0};
+    lo = 0.0;
+    for (int q = 0; q < m; ++q) {
+        const double hi = q + 1 < m ? planck_fraction(g.gp.edges[q] * iT) : 1.0;
+        const double b = hi - lo;
+        lo = hi;
+        const double gr = a.k.dt_ch * rho * g.gp.kP[q];
+        const double Es = Es_of(q);
+        const double E1 = a.absorb ? Es / (1.0 + gr) : (Es + gr * b * L) / (1.0 + gr);
+        const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rho * (g.gp.kR[q] + g.gp.sigma));
+        double F1[3], Fs[3];
+        for (int v = 0; v < 3; ++v) {
+            Fs[v] = double(reinterpret_cast<const R *>(g.star + (4 * q + 1 + v) * g.plane)[id]);
+            F1[v] = Fs[v] * inv_damp;
+        }
+        const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
+        if (Fn > E1) {
+            const double sc = E1 / Fn;
+            F1[0] *= sc;
+            F1[1] *= sc;
+            F1[2] *= sc;
+            atomicAdd(&a.cnt[2], 1ull);
+        }
+        const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
+        dE += double(E1r) - Es;
+        for (int v = 0; v < 3; ++v) dF[v] += double(F1r[v]) - Fs[v];
+        a.E[q * g.N + id] = E1r;
+        a.Fx[q * g.N + id] = F1r[0];
+        a.Fy[q * g.N + id] = F1r[1];
+        a.Fz[q * g.N + id] = F1r[2];
+    }
+    a.Eg[id] = Eg + S - a.k.c_ratio * dE;
+    a.mx[id] = mx - dF[0] * a.k.inv_ch;
+    a.my[id] = my - dF[1] * a.k.inv_ch;
+    a.mz[id] = mz - dF[2] * a.k.inv_ch;
+}
+
+template <typename R>
+static MgArgs<R> mg_args(m1_ctx *c)
+{
+    MgArgs<R> g;
+    g.gp = c->grp;
+    g.N = long(c->n[0]) * c->n[1] * c->n[2];
+    g.plane = c->plane_bytes;
+    g.star = static_cast<const unsigned char *>(c->star[0]);
+    return g;
+}
+
+template <typename R>
+static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met)
+{
+    IArgs<R> a;
+    fill_args(c, a, met, dt);
+    const MgArgs<R> g = mg_args<R>(c);
+    hipLaunchKernelGGL((k_implicit_mg<R>), dim3(unsigned((g.N + 255) / 256)), dim3(256), 0, c->stream, a, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_implicit(m1_ctx *c, double dt)
 {
+    if (c->grp.m > 1) {
+        if (c->par.precision == M1_F32) return launch_i_mg<float>(c, dt, c->met32);
+        return launch_i_mg<double>(c, dt, c->met64);
+    }
     if (c->par.precision == M1_F32) return launch_i<float>(c, dt, c->met32);
     return launch_i<double>(c, dt, c->met64);
 }
@@ -292,8 +452,23 @@ static hipError_t launch_init(m1_ctx *c, const Metric<R> &met)
     return hipGetLastError();
 }
 
+template <typename R>
+static hipError_t launch_init_mg(m1_ctx *c, const Metric<R> &met)
+{
+    IArgs<R> a;
+    fill_args(c, a, met, 0.0);
+    const MgArgs<R> g = mg_args<R>(c);
+    hipLaunchKernelGGL((k_tau_mg<R>), dim3(unsigned((g.N + 255) / 256)), dim3(256), 0, c->stream, a, g,
+                       static_cast<unsigned char *>(c->tau));
+    return hipGetLastError();
+}
+
 hipError_t launch_opacity_init(m1_ctx *c)
 {
+    if (c->grp.m > 1) {
+        if (c->par.precision == M1_F32) return launch_init_mg<float>(c, c->met32);
+        return launch_init_mg<double>(c, c->met64);
+    }
     if (c->par.precision == M1_F32) return launch_init<float>(c, c->met32);
     return launch_init<double>(c, c->met64);
 }

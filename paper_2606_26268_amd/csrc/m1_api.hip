@@ -342,7 +342,10 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     const size_t es = elem_size(c);
     const size_t per = ((N * es + 255) / 256) * 256;
     const size_t ndiag = (1024 + 1) * 8;
-    const size_t bytes = 6 * per + 256 + ndiag * sizeof(double);
+    // transported state and optical depth per group, the rho kappa_P cache
+    const int G = c->grp.m;
+    const size_t nfield = 5 * (size_t)G + 1;
+    const size_t bytes = nfield * per + 256 + ndiag * sizeof(double);
     if (c->scratch) {
         hipFree(c->scratch);
         c->scratch = nullptr;
@@ -350,11 +353,14 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     hipError_t e = hipMalloc(&c->scratch, bytes);
     if (e != hipSuccess) return fail(M1_ENOMEM, "m1_bind_state: scratch allocation failed");
     unsigned char *b = static_cast<unsigned char *>(c->scratch);
+    // layout: star (group g, field v) at (4 g + v) per, tau of group g at
+    // (4 G + g) per, rho kappa_P at 5 G per
+    c->plane_bytes = per;
     for (int v = 0; v < 4; ++v) c->star[v] = b + v * per;
-    c->tau = b + 4 * per;
-    c->rkp = b + 5 * per;
-    c->cnt = reinterpret_cast<unsigned long long *>(b + 6 * per);
-    c->partials = reinterpret_cast<double *>(b + 6 * per + 256);
+    c->tau = b + 4 * (size_t)G * per;
+    c->rkp = b + 5 * (size_t)G * per;
+    c->cnt = reinterpret_cast<unsigned long long *>(b + nfield * per);
+    c->partials = reinterpret_cast<double *>(b + nfield * per + 256);
     e = hipMemsetAsync(c->cnt, 0, 4 * sizeof(unsigned long long), c->stream);
     if (e != hipSuccess) return hip_fail(e, "m1_bind_state: counter reset");
     c->f = *f;
@@ -477,6 +483,7 @@ m1_status m1_mlp_gradient(m1_ctx *c, const float *samples, long n, const float *
 m1_status m1_opacity_eval(m1_ctx *c, long n, const double *rho, const double *T, double *kP, double *kR)
 {
     if (!c || n < 0 || (n > 0 && (!rho || !T || !kP || !kR))) return fail(M1_EINVAL, "m1_opacity_eval: bad argument");
+    if (c->grp.m > 1) return fail(M1_ENOTSUP, "m1_opacity_eval: the gray opacity model is unused with groups");
     hipError_t e = launch_opacity_eval(c, n, rho, T, kP, kR);
     if (e != hipSuccess) return hip_fail(e, "m1_opacity_eval");
     return M1_OK;
@@ -498,6 +505,34 @@ m1_status m1_max_dt(const m1_ctx *c, double cfl, double *dt)
                 worst = s > worst ? s : worst;
             }
     *dt = cfl / (c->c_hat * worst);
+    return M1_OK;
+}
+
+m1_status m1_set_groups(m1_ctx *c, int m, const double *edges, const double *kP, const double *kR,
+                        double sigma)
+{
+    if (!c) return fail(M1_EINVAL, "m1_set_groups: NULL context");
+    if (c->bound) return fail(M1_ESTATE, "m1_set_groups: call before m1_bind_state");
+    if (m < 1 || m > M1_MAX_GROUPS) return fail(M1_EINVAL, "m1_set_groups: need 1 <= m <= M1_MAX_GROUPS");
+    if (m == 1) {
+        c->grp.m = 1;
+        return M1_OK;
+    }
+    if (!edges || !kP || !kR) return fail(M1_EINVAL, "m1_set_groups: NULL array");
+    for (int g = 0; g + 1 < m; ++g)
+        if (!(edges[g] > 0) || !std::isfinite(edges[g]) || (g > 0 && !(edges[g] > edges[g - 1])))
+            return fail(M1_EINVAL, "m1_set_groups: edges must be positive and increasing");
+    for (int g = 0; g < m; ++g)
+        if (!(kP[g] >= 0) || !(kR[g] >= 0) || !std::isfinite(kP[g]) || !std::isfinite(kR[g]))
+            return fail(M1_EINVAL, "m1_set_groups: opacities must be finite and >= 0");
+    if (!(sigma >= 0)) return fail(M1_EINVAL, "m1_set_groups: sigma must be >= 0");
+    c->grp.m = m;
+    for (int g = 0; g < m; ++g) {
+        c->grp.edges[g] = g + 1 < m ? edges[g] : 0.0;
+        c->grp.kP[g] = kP[g];
+        c->grp.kR[g] = kR[g];
+    }
+    c->grp.sigma = sigma;
     return M1_OK;
 }
 
@@ -564,6 +599,7 @@ m1_status m1_step_rk2(m1_ctx *c, double dt)
     if (!c->bound) return fail(M1_ESTATE, "m1_step_rk2: no state bound");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(M1_EINVAL, "m1_step_rk2: dt must be > 0");
     if (!fixed_states_ready(c)) return fail(M1_ESTATE, "m1_step_rk2: a fixed boundary has no state");
+    if (c->grp.m > 1) return fail(M1_ENOTSUP, "m1_step_rk2: not available for multigroup states");
     const long N = ncells(c);
     const size_t per = ((N * elem_size(c) + 255) / 256) * 256;
     if (!c->rk2_save) {
@@ -599,6 +635,7 @@ m1_status m1_transported(m1_ctx *c, void **E, void **Fx, void **Fy, void **Fz)
 {
     if (!c || !E || !Fx || !Fy || !Fz) return fail(M1_EINVAL, "m1_transported: NULL argument");
     if (!c->bound) return fail(M1_ESTATE, "m1_transported: no state bound");
+    if (c->grp.m > 1) return fail(M1_ENOTSUP, "m1_transported: gray states only");
     *E = c->star[0];
     *Fx = c->star[1];
     *Fy = c->star[2];

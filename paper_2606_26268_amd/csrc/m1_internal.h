@@ -40,6 +40,14 @@ struct OpacityParams {
     double norm[4];
 };
 
+// multigroup parameters (constant group opacities, interior band edges)
+struct GroupParams {
+    int m;
+    double edges[M1_MAX_GROUPS];
+    double kP[M1_MAX_GROUPS], kR[M1_MAX_GROUPS];
+    double sigma;
+};
+
 struct ImplicitConsts {
     double dt, c_hat, c, a, gamma;
     double gm1, inv_gm1;        // gamma - 1 and its reciprocal
@@ -69,6 +77,8 @@ struct m1_ctx {
     double bc_state[3][2][4] = {};         // ghost state of fixed sides
     bool bc_state_set[3][2] = {};
     const double *irr = nullptr;           // irradiation heating per cell (caller's)
+    m1::GroupParams grp{1, {}, {}, {}, 0.0};   // m > 1: multigroup
+    size_t plane_bytes = 0;                // per-field stride of the scratch arrays
 
     // bound state
     bool bound = false;

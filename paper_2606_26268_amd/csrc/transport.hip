@@ -485,16 +485,21 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     }
 }
 
+// One transport launch for group g (g = 0 for gray states): the caller's
+// group arrays start at g n0 n1 n2, the scratch arrays are laid out per
+// group (transported fields 4 g + v, optical depth of group g).
 template <typename R>
-static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
+static hipError_t launch_t_group(m1_ctx *c, double dt, const Metric<R> &met, int g)
 {
     TArgs<R> a;
-    for (int v = 0; v < 4; ++v) a.out[v] = static_cast<R *>(c->star[v]);
-    a.U[0] = static_cast<const R *>(c->f.E);
-    a.U[1] = static_cast<const R *>(c->f.Fx);
-    a.U[2] = static_cast<const R *>(c->f.Fy);
-    a.U[3] = static_cast<const R *>(c->f.Fz);
-    a.tau = static_cast<const R *>(c->tau);
+    const long N = long(c->n[0]) * c->n[1] * c->n[2];
+    unsigned char *sb = static_cast<unsigned char *>(c->star[0]);
+    for (int v = 0; v < 4; ++v) a.out[v] = reinterpret_cast<R *>(sb + (4 * (size_t)g + v) * c->plane_bytes);
+    a.U[0] = static_cast<const R *>(c->f.E) + g * N;
+    a.U[1] = static_cast<const R *>(c->f.Fx) + g * N;
+    a.U[2] = static_cast<const R *>(c->f.Fy) + g * N;
+    a.U[3] = static_cast<const R *>(c->f.Fz) + g * N;
+    a.tau = reinterpret_cast<const R *>(static_cast<const unsigned char *>(c->tau) + g * c->plane_bytes);
     for (int d = 0; d < 3; ++d) {
         a.n[d] = c->n[d];
         a.bc[d][0] = c->bc[d][0];
@@ -514,7 +519,6 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
             for (int v = 0; v < 4; ++v) a.bcs[d][sd][v] = R(c->bc_state[d][sd][v]);
         }
     a.cnt = c->cnt;
-    const int N = c->n[0] * c->n[1] * c->n[2];
     if (c->ndim == 3) {
         const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
         // planes per block: enough blocks to fill the chip several times over
@@ -540,7 +544,7 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
 #undef M1_T3D
         return hipGetLastError();
     }
-    dim3 block(256), grid((N + 255) / 256);
+    dim3 block(256), grid(unsigned((N + 255) / 256));
 #define M1_LAUNCH(ND, G) \
     hipLaunchKernelGGL((k_transport<R, ND, G>), grid, block, 0, c->stream, a)
 #define M1_GEOMS(ND)                                                      \
@@ -557,6 +561,16 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
 #undef M1_GEOMS
 #undef M1_LAUNCH
     return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
+{
+    for (int g = 0; g < c->grp.m; ++g) {
+        hipError_t e = launch_t_group<R>(c, dt, met, g);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_transport(m1_ctx *c, double dt)

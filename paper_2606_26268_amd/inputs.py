@@ -387,6 +387,27 @@ def make_shadow(nx=140, ny=40, absorb_only=1, t_end=2.0, cfl=0.4, a_rad=1e-12):
     return p
 
 
+def make_multigroup(m=8, n=(128, 128, 128), seed=6, dt=None, steps=20):
+    """Multigroup workload: the c1 turbulent-box recipe (seeded fields, periodic
+    unit box) with the radiation split into m groups by seeded random
+    fractions (each group keeps f <= 0.5).  Group edges are log-spaced
+    between 0.3 and 20 (h nu / k in the temperature unit), Planck opacities
+    log-spaced from 0.1 to 30, Rosseland from 0.3 to 10, scattering 0.1."""
+    N = n[0]
+    p = make_turbulent_box(N, seed, 5.2083e-5 * 128 / N if dt is None else dt, steps, f"mg{m}")
+    if tuple(n) != (N, N, N):
+        raise ValueError("cubic boxes only")
+    rng = np.random.Generator(np.random.PCG64(1000 + seed))
+    w = rng.uniform(0.5, 1.5, m)
+    w /= w.sum()
+    for k in ("E", "Fx", "Fy", "Fz"):
+        p.fields[k] = np.ascontiguousarray(np.stack([p.fields[k] * w[g] for g in range(m)]))
+    p.groups = dict(edges=list(np.geomspace(0.3, 20.0, m - 1)) if m > 1 else [],
+                    kP=list(np.geomspace(0.1, 30.0, m)), kR=list(np.geomspace(0.3, 10.0, m)))
+    p.opacity = dict(kind=OPAC_CONSTANT, kP=0.0, kR=0.0, sigma=0.1)
+    return p
+
+
 def make_uniform(geometry, n, ndim, E=1.0, F=(0.0, 0.0, 0.0), bc=PERIODIC,
                  faces=None, kP=0.0, kR=0.0, sigma=0.0, c_hat=1.0):
     """Spatially uniform radiation field on any grid (well-balance checks)."""

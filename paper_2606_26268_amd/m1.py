@@ -78,7 +78,7 @@ EXPORTS = ("m1_params_default", "m1_create", "m1_destroy", "m1_set_stream", "m1_
            "m1_set_opacity_model", "m1_set_opacity_table", "m1_set_opacity_mlp", "m1_mlp_train",
            "m1_mlp_get", "m1_mlp_gradient", "m1_opacity_eval", "m1_max_dt", "m1_step_explicit", "m1_step_implicit", "m1_step_rk2",
            "m1_transported", "m1_refresh_opacity", "m1_sync", "m1_diagnostics", "m1_last_error",
-           "m1_set_boundary_state", "m1_set_irradiation")
+           "m1_set_boundary_state", "m1_set_irradiation", "m1_set_groups")
 
 _lib = None
 
@@ -114,6 +114,7 @@ def lib():
             "m1_diagnostics": [vp, C.POINTER(m1_diag)],
             "m1_set_boundary_state": [vp, C.c_int, C.c_int, dp],
             "m1_set_irradiation": [vp, vp],
+            "m1_set_groups": [vp, C.c_int, dp, dp, dp, C.c_double],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -246,6 +247,15 @@ def m1_max_dt(ctx, cfl):
     return dt.value
 
 
+def m1_set_groups(ctx, m, edges, kP, kR, sigma=0.0):
+    e = np.ascontiguousarray(edges if m > 1 else [0.0], dtype=np.float64)
+    a = np.ascontiguousarray(kP, dtype=np.float64)
+    b = np.ascontiguousarray(kR, dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    _check(lib().m1_set_groups(ctx, int(m), e.ctypes.data_as(dp), a.ctypes.data_as(dp), b.ctypes.data_as(dp),
+                               float(sigma)))
+
+
 def m1_set_boundary_state(ctx, direction, side, state):
     st = (C.c_double * 4)(*[float(v) for v in state])
     _check(lib().m1_set_boundary_state(ctx, int(direction), int(side), st))
@@ -348,6 +358,9 @@ class Solver:
                 if mlp is None:
                     raise ValueError("MLP opacity needs weights (or call train_mlp)")
                 m1_set_opacity_mlp(self.ctx, mlp["theta"], mlp["norm"])
+        grp = getattr(prob, "groups", None)
+        if grp is not None and len(grp["kP"]) > 1:
+            m1_set_groups(self.ctx, len(grp["kP"]), grp["edges"], grp["kP"], grp["kR"], op.get("sigma", 0.0))
         m1_bind_state(self.ctx, self.t)
 
     def close(self):
@@ -374,8 +387,8 @@ class Solver:
 
     def state(self):
         self.sync()
-        shp = self.prob.shape
-        return {k: v.detach().to("cpu", torch.float64).numpy().reshape(shp) for k, v in self.t.items()}
+        return {k: v.detach().to("cpu", torch.float64).numpy().reshape(self.prob.fields[k].shape)
+                for k, v in self.t.items()}
 
     def transported(self):
         """Host copy of the library's transported state (E*, F*)."""

@@ -1,0 +1,96 @@
+"""GPU parity of the multigroup form (one gray fluid per group, the
+(m+1)^2 implicit system of Sect. 2.7) against the oracle, which assembles
+that system literally and solves it densely while the kernel eliminates its
+arrowhead structure; conservation through the library's diagnostics; the
+error paths."""
+import numpy as np
+import pytest
+
+from paper_2606_26268_amd import inputs as I
+from tests.gpu_common import TOL_P64, assert_close, assert_close_f32, say
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("E", "Fx", "Fy", "Fz", "mx", "my", "mz", "Eg")
+
+
+def _run_gpu(p, precision, steps):
+    from paper_2606_26268_amd import m1
+    s = m1.Solver(p, precision)
+    s.step(p.dt, steps)
+    st, d = s.state(), s.diagnostics()
+    s.close()
+    return st, d
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+@pytest.mark.parametrize("m", [2, 5])
+def test_multigroup_box_parity(orc, precision, m):
+    p = I.make_multigroup(m, (20, 20, 20), seed=3)
+    p.c = 10 * p.c_hat
+    say(f"case multigroup m={m} {precision} 20^3")
+    ref, _ = orc.Oracle(p).run_mg(p.fields, p.dt, 10)
+    got, _ = _run_gpu(p, precision, 10)
+    if precision == "p64":
+        assert_close(got, ref, TOL_P64, fields=FIELDS, label=f"mg{m}")
+    else:
+        assert_close_f32(got, ref, fields=FIELDS, label=f"mg{m}", gas_scale=10.0)
+
+
+def test_multigroup_spherical_irradiated_absorbing(orc):
+    """Spherical (r, theta) grid, three groups, irradiation heating, then the
+    absorption-only coupling."""
+    n = (30, 14, 1)
+    faces = [np.geomspace(1.0, 10.0, 31), np.linspace(0.2, np.pi - 0.2, 15), np.array([0.0, 2 * np.pi])]
+    p = I.make_random_state(I.SPHERICAL, n, 2, 17, faces, [[I.OUTFLOW] * 2, [I.OUTFLOW] * 2, [0, 0]],
+                            fmax=0.6, c_hat=2.0)
+    rng = np.random.default_rng(4)
+    w = np.array([0.2, 0.5, 0.3])
+    for k in ("E", "Fx", "Fy", "Fz"):
+        p.fields[k] = np.ascontiguousarray(np.stack([p.fields[k] * w[g] for g in range(3)]))
+    p.groups = dict(edges=[0.8, 3.0], kP=[0.5, 5.0, 20.0], kR=[1.0, 2.0, 8.0])
+    p.opacity = dict(kind=I.OPAC_CONSTANT, kP=0.0, kR=0.0, sigma=0.05)
+    p.irr = np.exp(rng.standard_normal(p.fields["rho"].shape))
+    o = orc.Oracle(p)
+    p.dt = o.max_dt(0.4)
+    for absorb in (0, 1):
+        p.absorb_only = absorb
+        say(f"case multigroup spherical absorb={absorb}")
+        ref, _ = orc.Oracle(p).run_mg(p.fields, p.dt, 8)
+        got, _ = _run_gpu(p, "p64", 8)
+        assert_close(got, ref, TOL_P64, fields=FIELDS, label=f"mg-sph-{absorb}")
+
+
+def test_multigroup_diagnostics_conserve_totals(orc):
+    from paper_2606_26268_amd import m1
+    p = I.make_multigroup(4, (24, 24, 24), seed=8)
+    p.c = 4 * p.c_hat
+    s = m1.Solver(p, "p64")
+    d0 = s.diagnostics()
+    s.step(p.dt, 6)
+    d1 = s.diagnostics()
+    st = s.state()
+    s.close()
+    V = (1.0 / 24) ** 3
+    assert abs(d1["total_energy"] - d0["total_energy"]) <= 1e-12 * d0["total_energy"]
+    assert abs(d1["rad_energy"] - V * st["E"].sum()) <= 1e-12 * d1["rad_energy"]
+    for q in range(3):
+        assert abs(d1["momentum"][q] - d0["momentum"][q]) <= 1e-12 * (abs(d0["momentum"][q]) + d0["rad_energy"])
+
+
+def test_multigroup_errors():
+    from paper_2606_26268_amd import m1
+    p = I.make_multigroup(3, (8, 8, 8), seed=1)
+    s = m1.Solver(p, "p64")
+    with pytest.raises(m1.M1Error) as e:
+        m1.m1_set_groups(s.ctx, 2, [1.0], [1.0, 1.0], [1.0, 1.0])
+    assert e.value.status == m1.M1_ESTATE
+    with pytest.raises(m1.M1Error) as e:
+        m1.m1_step_rk2(s.ctx, p.dt)
+    assert e.value.status == m1.M1_ENOTSUP
+    s.close()
+    q = I.make_multigroup(3, (8, 8, 8), seed=1)
+    q.groups["edges"] = [2.0, 1.0]
+    with pytest.raises(m1.M1Error) as e:
+        m1.Solver(q, "p64")
+    assert e.value.status == m1.M1_EINVAL

@@ -149,3 +149,19 @@ def test_multigroup_relaxes_towards_a_planck_spectrum(orc):
     assert np.allclose(Eg, b * T ** 4, rtol=1e-6), (Eg, b * T ** 4)
     # energy balance: 1.5 T + sum E = 1.5 * 2 + 4e-3
     assert abs(1.5 * T + Eg.sum() - (3.0 + 4e-3)) < 1e-12
+
+
+def test_multigroup_absorption_only(orc):
+    p = _mg_problem(3)
+    p.absorb_only = 1
+    o = orc.Oracle(p)
+    r, _ = o.run_mg(p.fields, p.dt, 1)
+    q = _mg_problem(3)
+    q.absorb_only = 1
+    q.groups = dict(q.groups, kP=[0.0] * 3)          # transport alone
+    t, _ = orc.Oracle(q).run_mg(q.fields, q.dt, 1)
+    for g in range(3):
+        kP = p.groups["kP"][g]
+        np.testing.assert_allclose(r["E"][g], t["E"][g] / (1 + p.dt * p.c_hat * kP * p.fields["rho"]), rtol=1e-14)
+    ratio = p.c / p.c_hat
+    np.testing.assert_allclose(r["Eg"] + ratio * r["E"].sum(axis=0), t["Eg"] + ratio * t["E"].sum(axis=0), rtol=1e-14)
