@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2606_26268_amd import inputs as I
-from tests.gpu_common import TOL_P64, assert_close, assert_close_f32, say
+from tests.gpu_common import TOL_P64, TOL_P64_F1, assert_close, assert_close_f32, say
 
 pytestmark = pytest.mark.gpu
 
@@ -29,10 +29,16 @@ def test_multigroup_box_parity(orc, precision, m):
     p = I.make_multigroup(m, (20, 20, 20), seed=3)
     p.c = 10 * p.c_hat
     say(f"case multigroup m={m} {precision} 20^3")
-    ref, _ = orc.Oracle(p).run_mg(p.fields, p.dt, 10)
+    ref, cnt = orc.Oracle(p).run_mg(p.fields, p.dt, 10)
     got, _ = _run_gpu(p, precision, 10)
     if precision == "p64":
-        assert_close(got, ref, TOL_P64, fields=FIELDS, label=f"mg{m}")
+        # strongly absorbing groups lose E faster than F is damped, and the
+        # f <= 1 rule then clips cells to f = 1 exactly, where the signal
+        # speeds are sqrt(1 - f)-sensitive to rounding: the f = 1 tolerance
+        # applies exactly when the oracle reports such clips
+        tol = TOL_P64 if cnt[1] + cnt[2] == 0 else TOL_P64_F1
+        say(f"  oracle f-clips after transport / implicit: {cnt[1]} / {cnt[2]}")
+        assert_close(got, ref, tol, fields=FIELDS, label=f"mg{m}")
     else:
         assert_close_f32(got, ref, fields=FIELDS, label=f"mg{m}", gas_scale=10.0)
 
@@ -56,9 +62,13 @@ def test_multigroup_spherical_irradiated_absorbing(orc):
     for absorb in (0, 1):
         p.absorb_only = absorb
         say(f"case multigroup spherical absorb={absorb}")
-        ref, _ = orc.Oracle(p).run_mg(p.fields, p.dt, 8)
+        ref, cnt = orc.Oracle(p).run_mg(p.fields, p.dt, 8)
         got, _ = _run_gpu(p, "p64", 8)
-        assert_close(got, ref, TOL_P64, fields=FIELDS, label=f"mg-sph-{absorb}")
+        # absorption without emission empties E faster than F: cells clipped
+        # to f = 1 (see the box test) take the f = 1 tolerance
+        tol = TOL_P64 if cnt[1] + cnt[2] == 0 else TOL_P64_F1
+        say(f"  oracle f-clips after transport / implicit: {cnt[1]} / {cnt[2]}")
+        assert_close(got, ref, tol, fields=FIELDS, label=f"mg-sph-{absorb}")
 
 
 def test_multigroup_diagnostics_conserve_totals(orc):
