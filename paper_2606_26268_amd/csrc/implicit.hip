@@ -233,6 +233,15 @@ static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met)
 // B_k the Bernoulli numbers); above: 1 minus the tail
 // sum_n e^{-n x} (x^3/n + 3 x^2/n^2 + 6 x/n^3 + 6/n^4), summed until the
 // terms drop below double precision.
+// 1/n for the Planck tail: exact reciprocals of the first integers from a
+// table, a division beyond it
+__device__ __forceinline__ double inv_int(int n, double dn)
+{
+    constexpr double T[17] = {0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9,
+                              1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16};
+    return n <= 16 ? T[n] : 1.0 / dn;
+}
+
 __device__ double planck_fraction(double x)
 {
     constexpr double NORM = 0.15398973382026503;   // 15 / pi^4
@@ -252,9 +261,9 @@ __device__ double planck_fraction(double x)
     }
     const double e1 = exp(-x);
     const double x2 = x * x, x3 = x2 * x;
-    double e = e1, tail = 0.0;
-    for (int n = 1; n <= 64 && e > 1e-18 * e1; ++n) {
-        const double rn = 1.0 / n;
+    double e = e1, tail = 0.0, dn = 1.0;
+    for (int n = 1; n <= 48 && e > 1e-18 * e1; ++n, dn += 1.0) {
+        const double rn = inv_int(n, dn);
         tail += e * rn * (x3 + rn * (3.0 * x2 + rn * (6.0 * x + rn * 6.0)));
         e *= e1;
     }
@@ -292,7 +301,7 @@ __global__ void __launch_bounds__(256) k_tau_mg(IArgs<R> a, MgArgs<R> g, unsigne
 //   L  = a (4 T^3 T' - 3 T^4) = a T^3 (C_v T + 4 S + 4 sum_g g_g E*_g / (1 + gr_g)) / D,
 //   E'_g = (E*_g + gr_g b_g L) / (1 + gr_g),
 // O(m) work and no cancellation.
-template <typename R>
+template <typename R, int MG>
 __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
 {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,51 +315,54 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
     const double S = a.irr ? a.irr[id] * a.k.dt : 0.0;
     const double aT3 = a.k.a * T * T * T;
     const double iT = 1.0 / T;
-    auto Es_of = [&](int q) { return double(reinterpret_cast<const R *>(g.star + 4 * q * g.plane)[id]); };
-    // pass 1: the reduced equation for the temperature
+    // pass 1: group fractions, transported energies and the reduced equation
+    // for the temperature (per-group values stay in registers: MG >= m)
+    double b[MG], Es[MG], inv1[MG];
     double D = Cv, Lnum = Cv * T + 4.0 * S, lo = 0.0;
-    for (int q = 0; q < m; ++q) {
-        const double hi = q + 1 < m ? planck_fraction(g.gp.edges[q] * iT) : 1.0;
-        const double b = hi - lo;
-        lo = hi;
-        const double kr = rho * g.gp.kP[q];
-        const double inv1 = 1.0 / (1.0 + a.k.dt_ch * kr);
-        const double gg = a.k.dt_c * kr;
-        D += 4.0 * gg * b * aT3 * inv1;
-        Lnum += 4.0 * gg * Es_of(q) * inv1;
+#pragma unroll
+    for (int q = 0; q < MG; ++q) {
+        if (q < m) {
+            const double hi = q + 1 < m ? planck_fraction(g.gp.edges[q] * iT) : 1.0;
+            b[q] = hi - lo;
+            lo = hi;
+            Es[q] = double(reinterpret_cast<const R *>(g.star + 4 * q * g.plane)[id]);
+            const double kr = rho * g.gp.kP[q];
+            inv1[q] = 1.0 / (1.0 + a.k.dt_ch * kr);
+            const double gg = a.k.dt_c * kr;
+            D += 4.0 * gg * b[q] * aT3 * inv1[q];
+            Lnum += 4.0 * gg * Es[q] * inv1[q];
+        }
     }
     const double L = aT3 * Lnum / D;
     // pass 2: group energies, damped fluxes, rescaled totals
     double dE = 0.0, dF[3] = {0.0, 0.0, 0.0};
-    lo = 0.0;
-    for (int q = 0; q < m; ++q) {
-        const double hi = q + 1 < m ? planck_fraction(g.gp.edges[q] * iT) : 1.0;
-        const double b = hi - lo;
-        lo = hi;
-        const double gr = a.k.dt_ch * rho * g.gp.kP[q];
-        const double Es = Es_of(q);
-        const double E1 = a.absorb ? Es / (1.0 + gr) : (Es + gr * b * L) / (1.0 + gr);
-        const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rho * (g.gp.kR[q] + g.gp.sigma));
-        double F1[3], Fs[3];
-        for (int v = 0; v < 3; ++v) {
-            Fs[v] = double(reinterpret_cast<const R *>(g.star + (4 * q + 1 + v) * g.plane)[id]);
-            F1[v] = Fs[v] * inv_damp;
+#pragma unroll
+    for (int q = 0; q < MG; ++q) {
+        if (q < m) {
+            const double gr = a.k.dt_ch * rho * g.gp.kP[q];
+            const double E1 = a.absorb ? Es[q] * inv1[q] : (Es[q] + gr * b[q] * L) * inv1[q];
+            const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rho * (g.gp.kR[q] + g.gp.sigma));
+            double F1[3], Fs[3];
+            for (int v = 0; v < 3; ++v) {
+                Fs[v] = double(reinterpret_cast<const R *>(g.star + (4 * q + 1 + v) * g.plane)[id]);
+                F1[v] = Fs[v] * inv_damp;
+            }
+            const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
+            if (Fn > E1) {
+                const double sc = E1 / Fn;
+                F1[0] *= sc;
+                F1[1] *= sc;
+                F1[2] *= sc;
+                atomicAdd(&a.cnt[2], 1ull);
+            }
+            const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
+            dE += double(E1r) - Es[q];
+            for (int v = 0; v < 3; ++v) dF[v] += double(F1r[v]) - Fs[v];
+            a.E[q * g.N + id] = E1r;
+            a.Fx[q * g.N + id] = F1r[0];
+            a.Fy[q * g.N + id] = F1r[1];
+            a.Fz[q * g.N + id] = F1r[2];
         }
-        const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
-        if (Fn > E1) {
-            const double sc = E1 / Fn;
-            F1[0] *= sc;
-            F1[1] *= sc;
-            F1[2] *= sc;
-            atomicAdd(&a.cnt[2], 1ull);
-        }
-        const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
-        dE += double(E1r) - Es;
-        for (int v = 0; v < 3; ++v) dF[v] += double(F1r[v]) - Fs[v];
-        a.E[q * g.N + id] = E1r;
-        a.Fx[q * g.N + id] = F1r[0];
-        a.Fy[q * g.N + id] = F1r[1];
-        a.Fz[q * g.N + id] = F1r[2];
     }
     a.Eg[id] = Eg + S - a.k.c_ratio * dE;
     a.mx[id] = mx - dF[0] * a.k.inv_ch;
@@ -375,7 +387,15 @@ static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met)
     IArgs<R> a;
     fill_args(c, a, met, dt);
     const MgArgs<R> g = mg_args<R>(c);
-    hipLaunchKernelGGL((k_implicit_mg<R>), dim3(unsigned((g.N + 255) / 256)), dim3(256), 0, c->stream, a, g);
+    const dim3 grid(unsigned((g.N + 255) / 256)), block(256);
+    if (g.gp.m <= 4)
+        hipLaunchKernelGGL((k_implicit_mg<R, 4>), grid, block, 0, c->stream, a, g);
+    else if (g.gp.m <= 8)
+        hipLaunchKernelGGL((k_implicit_mg<R, 8>), grid, block, 0, c->stream, a, g);
+    else if (g.gp.m <= 16)
+        hipLaunchKernelGGL((k_implicit_mg<R, 16>), grid, block, 0, c->stream, a, g);
+    else
+        hipLaunchKernelGGL((k_implicit_mg<R, 32>), grid, block, 0, c->stream, a, g);
     return hipGetLastError();
 }
 

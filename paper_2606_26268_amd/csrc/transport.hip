@@ -24,8 +24,23 @@ struct TArgs {
     int recon, riemann;
     int special;               // some side is reflective or fixed
     R bcs[3][2][4];            // ghost state of fixed sides
+    long gs_in, gs_out, gs_tau; // element strides between frequency groups
     unsigned long long *cnt;
 };
+
+// Frequency group of this block (grid y): offset the group's arrays.
+template <typename R>
+__device__ __forceinline__ void select_group(TArgs<R> &a)
+{
+    const long g = blockIdx.y;
+    if (g == 0) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        a.U[v] += g * a.gs_in;
+        a.out[v] += g * a.gs_out;
+    }
+    a.tau += g * a.gs_tau;
+}
 
 // index along one direction after applying the boundary condition: periodic
 // wrap, mirror image (reflective), or the edge cell (outflow and fixed,
@@ -190,6 +205,7 @@ __device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], con
 template <typename R, int NDIM, int GEOM>
 __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
 {
+    select_group(a);
     const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
     const int N = n0 * n1 * n2;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,6 +254,7 @@ constexpr int NSP = (NXS + NYS + NT - 1) / NT, NFP = (NXF + NYF + NT - 1) / NT;
 template <typename R, int GEOM, bool VARIANTS>
 __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
 {
+    select_group(a);
     // the default scheme (f-preserving fix + HLL) is a compile-time constant
     const int recon = VARIANTS ? a.recon : int(M1_RECON_FPRESERVE);
     const int riemann = VARIANTS ? a.riemann : int(M1_RIEMANN_HLL);
@@ -485,21 +502,25 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     }
 }
 
-// One transport launch for group g (g = 0 for gray states): the caller's
-// group arrays start at g n0 n1 n2, the scratch arrays are laid out per
-// group (transported fields 4 g + v, optical depth of group g).
+// One transport launch for every frequency group (grid y = group; one group
+// for gray states): the caller's group arrays start at g n0 n1 n2, the
+// scratch arrays are laid out per group (transported fields 4 g + v,
+// optical depth of group g).
 template <typename R>
-static hipError_t launch_t_group(m1_ctx *c, double dt, const Metric<R> &met, int g)
+static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
 {
     TArgs<R> a;
     const long N = long(c->n[0]) * c->n[1] * c->n[2];
-    unsigned char *sb = static_cast<unsigned char *>(c->star[0]);
-    for (int v = 0; v < 4; ++v) a.out[v] = reinterpret_cast<R *>(sb + (4 * (size_t)g + v) * c->plane_bytes);
-    a.U[0] = static_cast<const R *>(c->f.E) + g * N;
-    a.U[1] = static_cast<const R *>(c->f.Fx) + g * N;
-    a.U[2] = static_cast<const R *>(c->f.Fy) + g * N;
-    a.U[3] = static_cast<const R *>(c->f.Fz) + g * N;
-    a.tau = reinterpret_cast<const R *>(static_cast<const unsigned char *>(c->tau) + g * c->plane_bytes);
+    const unsigned ngrp = unsigned(c->grp.m);
+    for (int v = 0; v < 4; ++v) a.out[v] = static_cast<R *>(c->star[v]);
+    a.U[0] = static_cast<const R *>(c->f.E);
+    a.U[1] = static_cast<const R *>(c->f.Fx);
+    a.U[2] = static_cast<const R *>(c->f.Fy);
+    a.U[3] = static_cast<const R *>(c->f.Fz);
+    a.tau = static_cast<const R *>(c->tau);
+    a.gs_in = N;
+    a.gs_out = long(4 * c->plane_bytes / sizeof(R));
+    a.gs_tau = long(c->plane_bytes / sizeof(R));
     for (int d = 0; d < 3; ++d) {
         a.n[d] = c->n[d];
         a.bc[d][0] = c->bc[d][0];
@@ -527,8 +548,8 @@ static hipError_t launch_t_group(m1_ctx *c, double dt, const Metric<R> &met, int
         const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
         const int launched = ((nblocks + 7) / 8) * 8;
         const bool var = c->par.recon != M1_RECON_FPRESERVE || c->par.riemann != M1_RIEMANN_HLL;
-#define M1_T3D(G, V)                                                                                  \
-    hipLaunchKernelGGL((k_transport3d<R, G, V>), dim3(launched), dim3(NT), 0, c->stream, a, nz, tiles_x, \
+#define M1_T3D(GM, V)                                                                                    \
+    hipLaunchKernelGGL((k_transport3d<R, GM, V>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz, tiles_x, \
                        tiles_y, nblocks)
         switch (c->geom) {
         case M1_CARTESIAN:
@@ -544,7 +565,7 @@ static hipError_t launch_t_group(m1_ctx *c, double dt, const Metric<R> &met, int
 #undef M1_T3D
         return hipGetLastError();
     }
-    dim3 block(256), grid(unsigned((N + 255) / 256));
+    dim3 block(256), grid(unsigned((N + 255) / 256), ngrp);
 #define M1_LAUNCH(ND, G) \
     hipLaunchKernelGGL((k_transport<R, ND, G>), grid, block, 0, c->stream, a)
 #define M1_GEOMS(ND)                                                      \
@@ -561,16 +582,6 @@ static hipError_t launch_t_group(m1_ctx *c, double dt, const Metric<R> &met, int
 #undef M1_GEOMS
 #undef M1_LAUNCH
     return hipGetLastError();
-}
-
-template <typename R>
-static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
-{
-    for (int g = 0; g < c->grp.m; ++g) {
-        hipError_t e = launch_t_group<R>(c, dt, met, g);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
 }
 
 hipError_t launch_transport(m1_ctx *c, double dt)
