@@ -6,6 +6,10 @@
 // Levermore closure and signal speeds of both face states, the HLL flux with
 // the optical-depth limiter, and the conservative update with the geometric
 // sources of the flux equation in cylindrical / spherical coordinates.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "m1_internal.h"
 #include "m1_device.h"
 
@@ -251,13 +255,14 @@ constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX, NHALO = 2 * (2 * TY + 2 
 constexpr int NXS = TY * (TX + 2), NYS = (TY + 2) * TX;
 constexpr int NSP = (NXS + NYS + NT - 1) / NT, NFP = (NXF + NYF + NT - 1) / NT;
 
-template <typename R, int GEOM, bool VARIANTS>
+template <typename R, int GEOM, bool GENERAL>
 __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
 {
     select_group(a);
-    // the default scheme (f-preserving fix + HLL) is a compile-time constant
-    const int recon = VARIANTS ? a.recon : int(M1_RECON_FPRESERVE);
-    const int riemann = VARIANTS ? a.riemann : int(M1_RIEMANN_HLL);
+    // the default scheme (f-preserving fix + HLL, periodic / outflow sides)
+    // is compiled without the variant and ghost-state code
+    const int recon = GENERAL ? a.recon : int(M1_RECON_FPRESERVE);
+    const int riemann = GENERAL ? a.riemann : int(M1_RIEMANN_HLL);
     __shared__ R sq[4][HY][HX];
     __shared__ R st[HY][HX];
     __shared__ R ss[4][NXS + NYS];      // slopes: x tasks, then y tasks
@@ -297,13 +302,13 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     // ghost transformation of a state in this thread's column (x, y ghosts)
     // and in plane kk (z ghosts); halo cells are ghosts in x or y only
     auto fix_col = [&](int kk, R q[4]) {
-        if (!a.special) return;
+        if (!GENERAL || !a.special) return;
         ghost_fix(a, 0, i, n0, q);
         ghost_fix(a, 1, j, n1, q);
         ghost_fix(a, 2, kk, n2, q);
     };
     auto fix_halo = [&](R q[4]) {
-        if (!a.special) return;
+        if (!GENERAL || !a.special) return;
         ghost_fix(a, 0, x0 - 2 + hx, n0, q);
         ghost_fix(a, 1, y0 - 2 + hy, n1, q);
     };
@@ -502,6 +507,49 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     }
 }
 
+// Blocks of a kernel the whole device holds at once (occupancy per compute
+// unit times the compute units), cached per kernel and device.
+static int resident_blocks(const void *kern, int block)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({kern, dev});
+    if (it != cache.end()) return it->second;
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0) != hipSuccess || per < 1) per = 1;
+    return cache[{kern, dev}] = per * cus;
+}
+
+// Tiled 3D launch.  The planes per block (z chunk) minimise the estimated
+// time rounds x (planes + 1): blocks run in rounds of the resident block
+// count, each chunk also pays about one plane of start-up (its first z face
+// and slopes), so a chunk that fills the last round evenly beats a smaller
+// one with a half-empty tail.
+template <typename R, int GEOM, bool GENERAL>
+static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
+{
+    const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
+    const long slots = resident_blocks(reinterpret_cast<const void *>(&k_transport3d<R, GEOM, GENERAL>), NT);
+    int nz = 4;
+    double best = 1e300;
+    for (int z = 2; z <= 64; ++z) {
+        const long nb = long(tiles_x) * tiles_y * ((c->n[2] + z - 1) / z) * ngrp;
+        const double cost = double((nb + slots - 1) / slots) * (z + 1);
+        if (cost < best) {
+            best = cost;
+            nz = z;
+        }
+    }
+    const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
+    const int launched = ((nblocks + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_transport3d<R, GEOM, GENERAL>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz,
+                       tiles_x, tiles_y, nblocks);
+}
+
 // One transport launch for every frequency group (grid y = group; one group
 // for gray states): the caller's group arrays start at g n0 n1 n2, the
 // scratch arrays are laid out per group (transported fields 4 g + v,
@@ -541,16 +589,8 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
         }
     a.cnt = c->cnt;
     if (c->ndim == 3) {
-        const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
-        // planes per block: enough blocks to fill the chip several times over
-        int nz = 64;
-        while (nz > 4 && (long)tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz) < 2048) nz /= 2;
-        const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
-        const int launched = ((nblocks + 7) / 8) * 8;
-        const bool var = c->par.recon != M1_RECON_FPRESERVE || c->par.riemann != M1_RIEMANN_HLL;
-#define M1_T3D(GM, V)                                                                                    \
-    hipLaunchKernelGGL((k_transport3d<R, GM, V>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz, tiles_x, \
-                       tiles_y, nblocks)
+        const bool var = c->par.recon != M1_RECON_FPRESERVE || c->par.riemann != M1_RIEMANN_HLL || a.special;
+#define M1_T3D(GM, V) launch_tiled<R, GM, V>(c, a, ngrp)
         switch (c->geom) {
         case M1_CARTESIAN:
             if (var) M1_T3D(M1_CARTESIAN, true); else M1_T3D(M1_CARTESIAN, false);
