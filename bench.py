@@ -92,8 +92,10 @@ def train_surrogate(m1, I, torch, solver, steps):
     return rep
 
 
-def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None):
-    """Returns dict with cells/s and per-kernel average durations."""
+def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False):
+    """Returns dict with cells/s and per-kernel average durations (rk2: the
+    second-order step, timed as a whole; its per-kernel fields are those of
+    the split step on the same state)."""
     mlp = None
     if prob.opacity["kind"] == 3:
         # construct with the table, then train the surrogate in place
@@ -109,14 +111,17 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None):
     dt = prob.dt
     stream = s.stream
     for _ in range(W):
-        s.step(dt)
+        s.step(dt, rk2=rk2)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     t0 = time.perf_counter()
     for _ in range(K):
-        m1.m1_step_explicit(s.ctx, dt)
-        m1.m1_step_implicit(s.ctx, dt)
+        if rk2:
+            m1.m1_step_rk2(s.ctx, dt)
+        else:
+            m1.m1_step_explicit(s.ctx, dt)
+            m1.m1_step_implicit(s.ctx, dt)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -222,6 +227,17 @@ def main():
         for name, prec in (("c1_mg8_f32", "f32"), ("c1_mg8_p64", "p64")):
             log(f"form {name}")
             forms[name] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), prec, K, W)
+        # the second-order step (two split steps and the average) on the table form
+        log("form c3_f32_table_rk2")
+        forms["c3_f32_table_rk2"] = time_form(m1, torch, I.make_c3(), "f32", K, W, rk2=True)
+        # the general transport kernel: Lax-Friedrichs flux with the simple
+        # clip, reflective walls in x and irradiation heating
+        log("form c1_f32_general")
+        pg = I.make_c1()
+        pg.recon, pg.riemann = 2, 1
+        pg.bc = [[I.REFLECT, I.REFLECT], [I.PERIODIC, I.PERIODIC], [I.PERIODIC, I.PERIODIC]]
+        pg.irr = pg.fields["rho"] * 0.1
+        forms["c1_f32_general"] = time_form(m1, torch, pg, "f32", K, W)
 
     ncell = 192 * 96 * 192
     # both kernels of the headline form are bound by vector-ALU issue (the
@@ -246,8 +262,12 @@ def main():
     out_forms = {}
     for name, r in forms.items():
         prec = "f32" if "f32" in name else "p64"
-        kind = "const" if ("const" in name or "mg" in name) else "table"
+        kind = "const" if ("const" in name or "mg" in name or "general" in name) else "table"
         bps = algorithmic_bytes("transport", prec, kind) + algorithmic_bytes("implicit", prec, kind)
+        if "general" in name:
+            bps += 8                      # the irradiation heating array
+        if name.endswith("_rk2"):
+            bps *= 2                      # two split steps per second-order step
         if "_mg8_" in name:
             # per group: transport (E, F, tau in; E*, F* out) and E*, F* in / E, F out; gas once
             s = 4 if prec == "f32" else 8
