@@ -280,9 +280,10 @@ m1_status m1_set_irradiation(m1_ctx *ctx, const double *q);
 /* Second-order Runge-Kutta step of length dt built from the split step as in
  * Sect. 2.4 (every sub-step is transport then sources): U1 = S(T(U^n)),
  * U2 = S(T(U1)), U^{n+1} = (U^n + U2) / 2 for E, F, m and E_g (rho is
- * frozen), followed by an opacity-cache refresh at the averaged gas state.
- * Asynchronous.  Allocates its save buffer (the state at t^n) on first use.
- * M1_ESTATE if no state is bound. */
+ * frozen); the opacity cache ends at the averaged gas state.  U1 lives in a
+ * library buffer allocated on first use; the second stage writes the
+ * average directly into the bound arrays.  Asynchronous.  M1_ESTATE if no
+ * state is bound, M1_ENOTSUP for multigroup states. */
 m1_status m1_step_rk2(m1_ctx *ctx, double dt);
 
 /* Device pointers of the library's transported state E*, Fx*, Fy*, Fz*

@@ -27,6 +27,9 @@ struct IArgs {
     ImplicitConsts k;
     const double *irr;                // irradiation heating per cell, or null
     int absorb;                       // absorption without emission
+    const double *gin[4];             // gas read (mx, my, mz, E_g); the written arrays in place
+    const R *ravg[4];                 // second-order step: radiation written as (ravg + new) / 2, or null
+    const double *gavg[4];            // and the gas likewise
     unsigned long long *cnt;
 };
 
@@ -68,7 +71,7 @@ template <typename R, bool CONST_OPAC>
 __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i, int j, int k)
 {
     const double rho = a.rho[id];
-    double mx = a.mx[id], my = a.my[id], mz = a.mz[id], Eg = a.Eg[id];
+    double mx = a.gin[0][id], my = a.gin[1][id], mz = a.gin[2][id], Eg = a.gin[3][id];
     const double inv_rho = 1.0 / rho;
     const double Cv = rho * a.k.inv_gm1;
     const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
@@ -104,11 +107,21 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     }
     // stored (possibly float) values define the exchanged amounts, so the
     // rescaled totals E_g + (c/c_hat) E and m + F/c_hat are conserved
-    const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
+    R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
     Eg += S - a.k.c_ratio * (double(E1r) - Es);
     mx -= (double(F1r[0]) - Fs[0]) * a.k.inv_ch;
     my -= (double(F1r[1]) - Fs[1]) * a.k.inv_ch;
     mz -= (double(F1r[2]) - Fs[2]) * a.k.inv_ch;
+    if (a.ravg[0]) {
+        // second-order step: U^{n+1} = (U^n + U2) / 2 (the averaging partner
+        // is read before this cell is written)
+        E1r = R(0.5 * (double(a.ravg[0][id]) + double(E1r)));
+        for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(a.ravg[1 + v][id]) + double(F1r[v])));
+        mx = 0.5 * (a.gavg[0][id] + mx);
+        my = 0.5 * (a.gavg[1][id] + my);
+        mz = 0.5 * (a.gavg[2][id] + mz);
+        Eg = 0.5 * (a.gavg[3][id] + Eg);
+    }
     a.E[id] = E1r;
     a.Fx[id] = F1r[0];
     a.Fy[id] = F1r[1];
@@ -202,14 +215,62 @@ static void fill_args(m1_ctx *c, IArgs<R> &a, const Metric<R> &met, double dt)
     a.k.c_ratio = c->par.c * a.k.inv_ch;
     a.irr = c->irr;
     a.absorb = c->par.absorb_only;
+    a.gin[0] = a.mx;
+    a.gin[1] = a.my;
+    a.gin[2] = a.mz;
+    a.gin[3] = a.Eg;
+    for (int v = 0; v < 4; ++v) {
+        a.ravg[v] = nullptr;
+        a.gavg[v] = nullptr;
+    }
     a.cnt = c->cnt;
 }
 
+// Stage of the second-order step (stage 0: an ordinary in-place step).
+// Stage 1 reads the caller's gas and writes U1 (radiation and gas) to the
+// save buffer; stage 2 reads U1's gas from there and writes (U^n + U2) / 2
+// into the caller's arrays, the opacity cache following the written state.
 template <typename R>
-static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met)
+static void rk2_stage_args(m1_ctx *c, IArgs<R> &a, int stage)
+{
+    if (stage == 0) return;
+    const long N = long(c->n[0]) * c->n[1] * c->n[2];
+    unsigned char *sv = static_cast<unsigned char *>(c->rk2_save);
+    R *srad[4];
+    double *sgas[4];
+    for (int v = 0; v < 4; ++v) {
+        srad[v] = reinterpret_cast<R *>(sv + v * c->plane_bytes);
+        sgas[v] = reinterpret_cast<double *>(sv + 4 * c->plane_bytes) + v * N;
+    }
+    if (stage == 1) {
+        a.E = srad[0];
+        a.Fx = srad[1];
+        a.Fy = srad[2];
+        a.Fz = srad[3];
+        a.mx = sgas[0];
+        a.my = sgas[1];
+        a.mz = sgas[2];
+        a.Eg = sgas[3];
+        const double *g[4] = {c->f.mx, c->f.my, c->f.mz, c->f.Eg};
+        for (int v = 0; v < 4; ++v) a.gin[v] = g[v];
+    } else {
+        const R *r[4] = {static_cast<const R *>(c->f.E), static_cast<const R *>(c->f.Fx),
+                         static_cast<const R *>(c->f.Fy), static_cast<const R *>(c->f.Fz)};
+        const double *g[4] = {c->f.mx, c->f.my, c->f.mz, c->f.Eg};
+        for (int v = 0; v < 4; ++v) {
+            a.gin[v] = sgas[v];
+            a.ravg[v] = r[v];
+            a.gavg[v] = g[v];
+        }
+    }
+}
+
+template <typename R>
+static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met, int stage = 0)
 {
     IArgs<R> a;
     fill_args(c, a, met, dt);
+    rk2_stage_args(c, a, stage);
     const int N = c->n[0] * c->n[1] * c->n[2];
     dim3 block(256), grid((N + 255) / 256);
     switch (c->op.kind) {
@@ -399,6 +460,12 @@ static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met)
     return hipGetLastError();
 }
 
+hipError_t launch_implicit_rk2(m1_ctx *c, double dt, int stage)
+{
+    if (c->par.precision == M1_F32) return launch_i<float>(c, dt, c->met32, stage);
+    return launch_i<double>(c, dt, c->met64, stage);
+}
+
 hipError_t launch_implicit(m1_ctx *c, double dt)
 {
     if (c->grp.m > 1) {
@@ -549,43 +616,6 @@ hipError_t launch_opacity_eval(m1_ctx *c, long n, const double *rho, const doubl
 // ---------------------------------------------------------------------------
 // RK2 averaging: U <- (U_saved + U) / 2 for E, F (form precision) and m, E_g
 // ---------------------------------------------------------------------------
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_rk2_average(R *E, R *Fx, R *Fy, R *Fz, double *mx, double *my, double *mz,
-                                                     double *Eg, const unsigned char *save, long N, size_t per)
-{
-    const long id = blockIdx.x * 256L + threadIdx.x;
-    if (id >= N) return;
-    const R *sr[4] = {reinterpret_cast<const R *>(save), reinterpret_cast<const R *>(save + per),
-                      reinterpret_cast<const R *>(save + 2 * per), reinterpret_cast<const R *>(save + 3 * per)};
-    const double *sg = reinterpret_cast<const double *>(save + 4 * per);
-    E[id] = R(0.5) * (sr[0][id] + E[id]);
-    Fx[id] = R(0.5) * (sr[1][id] + Fx[id]);
-    Fy[id] = R(0.5) * (sr[2][id] + Fy[id]);
-    Fz[id] = R(0.5) * (sr[3][id] + Fz[id]);
-    mx[id] = 0.5 * (sg[id] + mx[id]);
-    my[id] = 0.5 * (sg[N + id] + my[id]);
-    mz[id] = 0.5 * (sg[2 * N + id] + mz[id]);
-    Eg[id] = 0.5 * (sg[3 * N + id] + Eg[id]);
-}
-
-hipError_t launch_rk2_average(m1_ctx *c)
-{
-    const long N = (long)c->n[0] * c->n[1] * c->n[2];
-    const size_t es = c->par.precision == M1_F32 ? 4 : 8;
-    const size_t per = ((N * es + 255) / 256) * 256;
-    dim3 block(256), grid((unsigned)((N + 255) / 256));
-    const unsigned char *sv = static_cast<const unsigned char *>(c->rk2_save);
-    if (c->par.precision == M1_F32)
-        hipLaunchKernelGGL((k_rk2_average<float>), grid, block, 0, c->stream, static_cast<float *>(c->f.E),
-                           static_cast<float *>(c->f.Fx), static_cast<float *>(c->f.Fy), static_cast<float *>(c->f.Fz),
-                           c->f.mx, c->f.my, c->f.mz, c->f.Eg, sv, N, per);
-    else
-        hipLaunchKernelGGL((k_rk2_average<double>), grid, block, 0, c->stream, static_cast<double *>(c->f.E),
-                           static_cast<double *>(c->f.Fx), static_cast<double *>(c->f.Fy),
-                           static_cast<double *>(c->f.Fz), c->f.mx, c->f.my, c->f.mz, c->f.Eg, sv, N, per);
-    return hipGetLastError();
-}
 
 } // namespace m1
 

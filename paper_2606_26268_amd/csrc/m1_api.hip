@@ -609,24 +609,16 @@ m1_status m1_step_rk2(m1_ctx *c, double dt)
             return fail(M1_ENOMEM, "m1_step_rk2: save buffer allocation failed");
         }
     }
+    // U1 = S(T(U^n)) into the save buffer (the caller's arrays keep U^n),
+    // then U2 = S(T(U1)) written directly as (U^n + U2) / 2, the opacity
+    // cache following each stage's written state
     unsigned char *sv = static_cast<unsigned char *>(c->rk2_save);
-    void *rad[4] = {c->f.E, c->f.Fx, c->f.Fy, c->f.Fz};
-    double *gas[4] = {c->f.mx, c->f.my, c->f.mz, c->f.Eg};
-    hipError_t e = hipSuccess;
-    for (int v = 0; v < 4 && e == hipSuccess; ++v)
-        e = hipMemcpyAsync(sv + v * per, rad[v], N * elem_size(c), hipMemcpyDeviceToDevice, c->stream);
-    for (int v = 0; v < 4 && e == hipSuccess; ++v)
-        e = hipMemcpyAsync(sv + 4 * per + v * N * sizeof(double), gas[v], N * sizeof(double),
-                           hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "m1_step_rk2 save");
-    for (int stage = 0; stage < 2; ++stage) {
-        e = launch_transport(c, dt);
-        if (e == hipSuccess) e = launch_implicit(c, dt);
-        if (e != hipSuccess) return hip_fail(e, "m1_step_rk2 stage");
-    }
-    e = launch_rk2_average(c);
-    if (e == hipSuccess && c->op.kind != OPK_CONST) e = launch_opacity_init(c);
-    if (e != hipSuccess) return hip_fail(e, "m1_step_rk2 average");
+    const void *u1[4] = {sv, sv + per, sv + 2 * per, sv + 3 * per};
+    hipError_t e = launch_transport(c, dt);
+    if (e == hipSuccess) e = launch_implicit_rk2(c, dt, 1);
+    if (e == hipSuccess) e = launch_transport_from(c, dt, u1);
+    if (e == hipSuccess) e = launch_implicit_rk2(c, dt, 2);
+    if (e != hipSuccess) return hip_fail(e, "m1_step_rk2 stage");
     c->transported = false;
     return M1_OK;
 }

@@ -107,7 +107,8 @@ hipError_t launch_opacity_init(m1_ctx *c);
 hipError_t launch_opacity_eval(m1_ctx *c, long n, const double *rho, const double *T, double *kP,
                                double *kR);
 hipError_t launch_diag(m1_ctx *c, double out[8]);
-hipError_t launch_rk2_average(m1_ctx *c);
+hipError_t launch_implicit_rk2(m1_ctx *c, double dt, int stage);
+hipError_t launch_transport_from(m1_ctx *c, double dt, const void *const rad[4]);
 int mlp_pack(m1_ctx *c, const float *theta, const double *norm);
 int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep);
 int mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, float *grad, double *loss);

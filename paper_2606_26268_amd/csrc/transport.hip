@@ -555,16 +555,14 @@ static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
 // scratch arrays are laid out per group (transported fields 4 g + v,
 // optical depth of group g).
 template <typename R>
-static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met)
+static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met, const void *const rad[4] = nullptr)
 {
     TArgs<R> a;
     const long N = long(c->n[0]) * c->n[1] * c->n[2];
     const unsigned ngrp = unsigned(c->grp.m);
     for (int v = 0; v < 4; ++v) a.out[v] = static_cast<R *>(c->star[v]);
-    a.U[0] = static_cast<const R *>(c->f.E);
-    a.U[1] = static_cast<const R *>(c->f.Fx);
-    a.U[2] = static_cast<const R *>(c->f.Fy);
-    a.U[3] = static_cast<const R *>(c->f.Fz);
+    const void *src[4] = {c->f.E, c->f.Fx, c->f.Fy, c->f.Fz};
+    for (int v = 0; v < 4; ++v) a.U[v] = static_cast<const R *>(rad ? rad[v] : src[v]);
     a.tau = static_cast<const R *>(c->tau);
     a.gs_in = N;
     a.gs_out = long(4 * c->plane_bytes / sizeof(R));
@@ -628,6 +626,13 @@ hipError_t launch_transport(m1_ctx *c, double dt)
 {
     if (c->par.precision == M1_F32) return launch_t<float>(c, dt, c->met32);
     return launch_t<double>(c, dt, c->met64);
+}
+
+// transport of a state held elsewhere (the second-order step's U1)
+hipError_t launch_transport_from(m1_ctx *c, double dt, const void *const rad[4])
+{
+    if (c->par.precision == M1_F32) return launch_t<float>(c, dt, c->met32, rad);
+    return launch_t<double>(c, dt, c->met64, rad);
 }
 
 } // namespace m1
