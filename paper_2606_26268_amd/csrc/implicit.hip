@@ -93,8 +93,14 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     const double aT3 = a.k.a * T * T * T, aT4 = aT3 * T;
     const double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
     // irradiation energy deposited in the step enters the S_1 row (Sect. 2.8)
-    const double S = a.irr ? a.irr[id] * a.k.dt : 0.0;
-    double E1 = a.absorb ? Es / (1.0 + gr) : (Cv * (Es + gr * aT4) + 4.0 * aT3 * (g * Es + gr * S)) / det;
+    double S = 0.0;
+    if (a.irr) S = a.irr[id] * a.k.dt;
+    // uniform branch: the absorption-only form costs the default path nothing
+    double E1;
+    if (a.absorb)
+        E1 = Es / (1.0 + gr);
+    else
+        E1 = (Cv * (Es + gr * aT4) + 4.0 * aT3 * (g * Es + gr * S)) / det;
     const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rchi);   // Eq. source_discrete2
     double F1[3] = {Fs[0] * inv_damp, Fs[1] * inv_damp, Fs[2] * inv_damp};
     const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
