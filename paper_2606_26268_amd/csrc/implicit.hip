@@ -159,7 +159,10 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
 
 // MLP opacity: every lane of a wavefront takes part in the network
 // evaluation (one 64-cell chunk per wavefront), so lanes past the last cell
-// compute on a clamped index instead of exiting early.
+// compute on a clamped index instead of exiting early.  The cell update runs
+// before the weights are staged into LDS: its many array pointers are then
+// dead during the staging, which keeps the kernel within the scalar register
+// file (staged first, the pointers were spilled to vector lanes).
 template <typename R>
 __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
 {
@@ -167,8 +170,6 @@ __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
     const int N = n0 * n1 * a.n[2];
     const int lane = threadIdx.x & 63;
     __shared__ MlpShared sh;
-    mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
-    __syncthreads();
     {
         const int id = blockIdx.x * blockDim.x + threadIdx.x;
         const bool live = id < N;
@@ -177,6 +178,8 @@ __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
         double T1 = 1.0;
         if (live) T1 = implicit_cell<R, false>(a, id, i, j, k);
         const float rho = float(a.rho[idc]);
+        mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
+        __syncthreads();
         float kP, kR;
         mlp_opacity_shared(a.op, sh, rho, float(T1), lane, kP, kR);
         if (live) {
