@@ -92,10 +92,11 @@ def train_surrogate(m1, I, torch, solver, steps):
     return rep
 
 
-def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False):
+def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False, keep=False):
     """Returns dict with cells/s and per-kernel average durations (rk2: the
     second-order step, timed as a whole; its per-kernel fields are those of
-    the split step on the same state)."""
+    the split step on the same state).  keep: also return the final state
+    (device copies in FP64) for comparing forms run on the same input."""
     mlp = None
     if prob.opacity["kind"] == 3:
         # construct with the table, then train the surrogate in place
@@ -138,10 +139,41 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=F
     t_tr = sum(ev[k][0].elapsed_time(ev[k][1]) for k in range(K)) / K
     t_im = sum(ev[k][1].elapsed_time(ev[k][2]) for k in range(K)) / K
     d = s.diagnostics()
+    final = {k: v.detach().to(torch.float64).clone() for k, v in s.t.items() if k != "rho"} if keep else None
     s.close()
     n = prob.ncells
     return dict(cells_per_s=n * K / (ms * 1e-3), ms_per_step=ms / K, wall_s=wall,
-                transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp)
+                transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp, state=final)
+
+
+def field_errors(a, b):
+    """Per field of state a against state b: [sum |a - b| / sum |b|,
+    max |a - b| / max |b|] (fields of b that are zero everywhere: absolute)."""
+    out = {}
+    for k, ref in b.items():
+        d = (a[k] - ref).abs()
+        l1, mx = float(ref.abs().sum()), float(ref.abs().max())
+        out[k] = [float(d.sum()) / (l1 if l1 > 0 else 1.0), float(d.max()) / (mx if mx > 0 else 1.0)]
+    return out
+
+
+def copy_bandwidth(torch, n=1 << 28, reps=10):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of
+    a 1 GiB FP32 array on this GPU, timed with events."""
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 8.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def source_hash(kernel):
@@ -179,12 +211,15 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
-def oracle_baseline(I, seconds_target=15.0):
+def oracle_baseline(I, seconds_target=15.0, threads=None, shape=(96, 48, 96)):
     """The FP64 oracle on a bounded sample of the headline workload: the
-    same spherical recipe with the MLP surrogate on a 96x48x96 grid."""
+    same spherical recipe with the MLP surrogate on a reduced grid, with all
+    host threads (threads=None) or the given number."""
     import numpy as np
     from oracle import oracle as orc
-    p = I.make_c4(nr=96, nth=48, nph=96)
+    if threads is not None:
+        orc.set_threads(threads)
+    p = I.make_c4(nr=shape[0], nth=shape[1], nph=shape[2])
     tab = p.opacity
     a = tab["log10_kP"].astype(np.float64)
     b = tab["log10_kR"].astype(np.float64)
@@ -197,9 +232,22 @@ def oracle_baseline(I, seconds_target=15.0):
         st, _ = o.run(st, p.dt, 1)
         t += time.perf_counter() - t0
         steps += 1
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = orc.max_threads()
+    shp = "x".join(str(v) for v in shape)
     return dict(value=p.ncells * steps / t, unit="cell updates/s", cores=cores, kind="oracle",
-                sample=f"spherical recipe with MLP opacity on 96x48x96 cells, {steps} steps, {t:.1f} s")
+                sample=f"spherical recipe with MLP opacity on {shp} cells, {steps} steps, {t:.1f} s")
+
+
+def compare_pair(forms, name):
+    """Once both the FP32 and the FP64 run of a workload are done (same
+    input, same steps), store the FP32 result's per-field deviation from the
+    FP64 one with the FP32 form and release both final states."""
+    other = name.replace("f32", "p64") if "f32" in name else name.replace("p64", "f32")
+    if other not in forms:
+        return
+    f32, p64 = (name, other) if "f32" in name else (other, name)
+    forms[f32]["vs_p64"] = field_errors(forms[f32]["state"], forms[p64]["state"])
+    forms[f32]["state"] = forms[p64]["state"] = None
 
 
 def main():
@@ -223,10 +271,12 @@ def main():
                                ("c1_p64_const", I.make_c1, "p64"), ("c1_f32_const", I.make_c1, "f32"),
                                ("c2_p64_const", I.make_c2, "p64"), ("c2_f32_const", I.make_c2, "f32")):
             log(f"form {name}")
-            forms[name] = time_form(m1, torch, mk(), prec, K, W)
+            forms[name] = time_form(m1, torch, mk(), prec, K, W, keep=True)
+            compare_pair(forms, name)
         for name, prec in (("c1_mg8_f32", "f32"), ("c1_mg8_p64", "p64")):
             log(f"form {name}")
-            forms[name] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), prec, K, W)
+            forms[name] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), prec, K, W, keep=True)
+            compare_pair(forms, name)
         # the second-order step (two split steps and the average) on the table form
         log("form c3_f32_table_rk2")
         forms["c3_f32_table_rk2"] = time_form(m1, torch, I.make_c3(), "f32", K, W, rk2=True)
@@ -240,6 +290,8 @@ def main():
         forms["c1_f32_general"] = time_form(m1, torch, pg, "f32", K, W)
 
     ncell = 192 * 96 * 192
+    # HBM fractions are also given against what a plain copy reaches here
+    copy_gbs = copy_bandwidth(torch)
     # both kernels of the headline form are bound by vector-ALU issue (the
     # counter runs under profiles/ show it); the roofline is that of the
     # longer one, with its HBM figures alongside
@@ -257,6 +309,7 @@ def main():
                     frac=round(k["tops"] / VALU_PEAK_TOPS, 4), traffic=k["traffic"], kernel=kern,
                     ms_per_launch=k["ms_per_launch"], algorithmic_ops_per_launch=k["algorithmic_ops_per_launch"],
                     hbm_achieved_gbs=round(k["hbm_gbs"], 1), hbm_frac=round(k["hbm_gbs"] / HBM_PEAK_GBS, 4),
+                    hbm_copy_gbs=round(copy_gbs, 1), hbm_frac_of_copy=round(k["hbm_gbs"] / copy_gbs, 4),
                     kernels=per_kernel)
 
     out_forms = {}
@@ -276,8 +329,16 @@ def main():
                                transport_ms=r["transport_ms"], implicit_ms=r["implicit_ms"],
                                bytes_per_cell_step=bps,
                                hbm_frac=r["cells_per_s"] * bps / (HBM_PEAK_GBS * 1e9),
+                               hbm_frac_of_copy=r["cells_per_s"] * bps / (copy_gbs * 1e9),
                                fixups=r["counters"][:3])
-    cpu = None if args.no_cpu else oracle_baseline(I)
+        if "vs_p64" in r:
+            out_forms[name]["vs_p64"] = {k: [float("%.3g" % v[0]), float("%.3g" % v[1])] for k, v in r["vs_p64"].items()}
+    cpu = None
+    if not args.no_cpu:
+        cpu = oracle_baseline(I)
+        if not args.only:
+            one = oracle_baseline(I, seconds_target=8.0, threads=1, shape=(48, 24, 48))
+            cpu["one_thread"] = dict(value=one["value"], sample=one["sample"])
     line = {
         "metric": "M1 cell updates/s (explicit+implicit), FP32/MLP form vs FP64 plain, 1 MI355X",
         "value": head["cells_per_s"],

@@ -407,3 +407,15 @@ def mg_cell(Es, Cv, T, kP, rho, dt, c_hat, c, a, b, S=0.0):
     if rc != 0:
         raise RuntimeError("singular multigroup system")
     return out
+
+
+def set_threads(n):
+    """Number of OpenMP threads the oracle's parallel loops use from now on
+    (results do not depend on it: cells are independent, sums are serial)."""
+    lib().omp_set_num_threads.argtypes = [C.c_int]
+    lib().omp_set_num_threads(int(n))
+
+
+def max_threads():
+    lib().omp_get_max_threads.restype = C.c_int
+    return int(lib().omp_get_max_threads())

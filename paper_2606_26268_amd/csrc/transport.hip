@@ -253,7 +253,23 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
 constexpr int TX = 32, TY = 8, HX = TX + 4, HY = TY + 4, NT = TX * TY;
 constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX, NHALO = 2 * (2 * TY + 2 * TX);
 constexpr int NXS = TY * (TX + 2), NYS = (TY + 2) * TX;
-constexpr int NSP = (NXS + NYS + NT - 1) / NT, NFP = (NXF + NYF + NT - 1) / NT;
+// Task passes of the slope and face stages: pass 0 takes x tasks 0 .. NT-1,
+// pass 1 y tasks 0 .. NT-1, pass 2 the rest of both (x first), so that the
+// first two passes run with their direction fixed at compile time.
+static_assert(NXF >= NT && NYF >= NT && NXS >= NT && NYS >= NT, "tile too small for the task passes");
+static_assert(NXF + NYF <= 3 * NT && NXS + NYS <= 3 * NT, "tile too large for three task passes");
+constexpr int NSP = 3, NFP = 3;
+
+// task of thread tid in pass p: direction (0 = x, 1 = y) and index within
+// that direction's tasks, or -1 past the last (nx, ny: task counts)
+__device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
+{
+    dir = p == 1 ? 1 : 0;
+    if (p < 2) return tid;
+    if (tid < nx - NT) return NT + tid;
+    dir = 1;
+    return tid - (nx - NT) < ny - NT ? NT + tid - (nx - NT) : -1;
+}
 
 template <typename R, int GEOM, bool GENERAL>
 __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
@@ -315,17 +331,18 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
 
     // slope tasks: centre cell in sq (flat), neighbour stride, inverse spacings.
     // Cells past the last ghost (m > n) feed no face and are skipped.
-    int s_ctr[NSP], s_str[NSP];
+    int s_ctr[NSP], s_str[NSP], s_slot[NSP];
     R s_wl[NSP], s_wr[NSP];
     bool s_on[NSP];
 #pragma unroll
     for (int p = 0; p < NSP; ++p) {
-        const int q = tid + p * NT;
+        int dir;
+        const int q = task_of(p, tid, NXS, NYS, dir);
         s_on[p] = false;
         s_ctr[p] = 2 * HX + 2;
         s_str[p] = 1;
         s_wl[p] = s_wr[p] = R(0);
-        if (q < NXS) {
+        if (q >= 0 && dir == 0) {
             const int r = q / (TX + 2), c = q % (TX + 2), m = x0 + c - 1;
             if (m <= n0) {
                 s_on[p] = true;
@@ -333,8 +350,8 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
                 s_wl[p] = a.m.winv[0][m + 2];
                 s_wr[p] = a.m.winv[0][m + 3];
             }
-        } else if (q < NXS + NYS) {
-            const int qq = q - NXS, r = qq / TX, c = qq % TX, m = y0 + r - 1;
+        } else if (q >= 0) {
+            const int qq = q, r = qq / TX, c = qq % TX, m = y0 + r - 1;
             if (m <= n1) {
                 s_on[p] = true;
                 s_ctr[p] = (r + 1) * HX + c + 2;
@@ -343,6 +360,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
                 s_wr[p] = a.m.winv[1][m + 3];
             }
         }
+        s_slot[p] = dir == 0 ? q : NXS + q;
     }
     // face tasks: direction, left donor in sq, its slope in ss, flux slot,
     // centre-to-face offsets of the two donors
@@ -351,12 +369,13 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     bool f_on[NFP];
 #pragma unroll
     for (int p = 0; p < NFP; ++p) {
-        const int q = tid + p * NT;
+        int dir;
+        const int q = task_of(p, tid, NXF, NYF, dir);
         f_on[p] = false;
         f_d[p] = 0;
         f_b[p] = f_sb[p] = f_o[p] = 0;
         f_hp[p] = f_hm[p] = R(0);
-        if (q < NXF) {
+        if (q >= 0 && dir == 0) {
             const int row = q / (TX + 1), fo = q % (TX + 1), g = x0 + fo;
             if (g <= n0 && y0 + row < n1) {
                 f_on[p] = true;
@@ -366,8 +385,8 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
                 f_hp[p] = a.m.hp[0][g + 1];
                 f_hm[p] = a.m.hm[0][g + 2];
             }
-        } else if (q < NXF + NYF) {
-            const int qq = q - NXF, go = qq / TX, cl = qq % TX, g = y0 + go;
+        } else if (q >= 0) {
+            const int qq = q, go = qq / TX, cl = qq % TX, g = y0 + go;
             if (g <= n1 && x0 + cl < n0) {
                 f_on[p] = true;
                 f_d[p] = 1;
@@ -445,15 +464,16 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         for (int p = 0; p < NSP; ++p) {
             if (!s_on[p]) continue;
             R qm[4], q0[4], qp[4], sl[4];
+            const int str = p == 0 ? 1 : (p == 1 ? HX : s_str[p]);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                qm[v] = sqf[v * QS + s_ctr[p] - s_str[p]];
+                qm[v] = sqf[v * QS + s_ctr[p] - str];
                 q0[v] = sqf[v * QS + s_ctr[p]];
-                qp[v] = sqf[v * QS + s_ctr[p] + s_str[p]];
+                qp[v] = sqf[v * QS + s_ctr[p] + str];
             }
             slopes4(qm, q0, qp, s_wl[p], s_wr[p], sl);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) ss[v][tid + p * NT] = sl[v];
+            for (int v = 0; v < 4; ++v) ss[v][s_slot[p]] = sl[v];
         }
         // z slope of plane k+1
         R Sz1[4];
@@ -464,7 +484,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
 #pragma unroll
         for (int p = 0; p < NFP; ++p) {
             if (!f_on[p]) continue;
-            const int d = f_d[p], b = f_b[p], sb = f_sb[p];
+            const int d = p < 2 ? p : f_d[p], b = f_b[p], sb = f_sb[p];
             const int qst = d ? HX : 1, sst = d ? TX : 1;
             R qb[4], qc[4], slb[4], slc[4], fl[4];
 #pragma unroll
