@@ -22,6 +22,7 @@ struct IArgs {
     R *rkp, *tau;                     // opacity cache (read at T^n, written at T^{n+1})
     int n[3];
     int ndim;
+    CellIndex ix;
     Metric<R> m;
     OpacityParams op;
     ImplicitConsts k;
@@ -65,14 +66,15 @@ __device__ __forceinline__ double gas_T_r(double inv_rho, double mx, double my, 
 }
 
 // One cell of the implicit step; returns the new gas temperature.  Four
-// FP64 divisions per cell: 1/rho, the determinant, the flux damping factor
-// and the optical depth per length.
+// FP64 reciprocals per cell (hardware estimate refined by two Newton steps,
+// about 1 ulp): 1/rho, the determinant, the flux damping factor and the
+// optical depth per length.
 template <typename R, bool CONST_OPAC>
 __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i, int j, int k)
 {
     const double rho = a.rho[id];
     double mx = a.gin[0][id], my = a.gin[1][id], mz = a.gin[2][id], Eg = a.gin[3][id];
-    const double inv_rho = 1.0 / rho;
+    const double inv_rho = Num<double>::rcp(rho);
     const double Cv = rho * a.k.inv_gm1;
     const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
     double rkP, rchi;
@@ -81,7 +83,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
         rchi = rho * (a.op.kR + a.op.sigma);
     } else {
         rkP = double(a.rkp[id]);
-        rchi = double(a.tau[id]) / double(cell_hmax(a.m, a.ndim, i, j, k));
+        rchi = double(a.tau[id]) * Num<double>::rcp(double(cell_hmax(a.m, a.ndim, i, j, k)));
     }
     const double Es = double(a.Es[id]);
     const double Fs[3] = {double(a.Fxs[id]), double(a.Fys[id]), double(a.Fzs[id])};
@@ -100,8 +102,8 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
     if (a.absorb)
         E1 = Es / (1.0 + gr);
     else
-        E1 = (Cv * (Es + gr * aT4) + 4.0 * aT3 * (g * Es + gr * S)) / det;
-    const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rchi);   // Eq. source_discrete2
+        E1 = (Cv * (Es + gr * aT4) + 4.0 * aT3 * (g * Es + gr * S)) * Num<double>::rcp(det);
+    const double inv_damp = Num<double>::rcp(1.0 + a.k.dt_ch * rchi);   // Eq. source_discrete2
     double F1[3] = {Fs[0] * inv_damp, Fs[1] * inv_damp, Fs[2] * inv_damp};
     const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
     if (Fn > E1) {
@@ -146,7 +148,8 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
     const int N = n0 * n1 * a.n[2];
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
-    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    int i, j, k;
+    a.ix.split(id, i, j, k);
     const double T1 = implicit_cell<R, OPK == OPK_CONST>(a, id, i, j, k);
     if (OPK != OPK_CONST) {
         const R rho = R(a.rho[id]);
@@ -174,7 +177,8 @@ __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
         const int id = blockIdx.x * blockDim.x + threadIdx.x;
         const bool live = id < N;
         const int idc = live ? id : N - 1;
-        const int i = idc % n0, j = (idc / n0) % n1, k = idc / (n0 * n1);
+        int i, j, k;
+        a.ix.split(idc, i, j, k);
         double T1 = 1.0;
         if (live) T1 = implicit_cell<R, false>(a, id, i, j, k);
         const float rho = float(a.rho[idc]);
@@ -209,6 +213,7 @@ static void fill_args(m1_ctx *c, IArgs<R> &a, const Metric<R> &met, double dt)
     a.tau = static_cast<R *>(c->tau);
     for (int d = 0; d < 3; ++d) a.n[d] = c->n[d];
     a.ndim = c->ndim;
+    a.ix.set(c->n[0], c->n[1]);
     a.m = met;
     a.op = c->op;
     a.k.dt = dt;
@@ -352,10 +357,10 @@ struct MgArgs {
 template <typename R>
 __global__ void __launch_bounds__(256) k_tau_mg(IArgs<R> a, MgArgs<R> g, unsigned char *tau)
 {
-    const int n0 = a.n[0], n1 = a.n[1];
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= g.N) return;
-    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    int i, j, k;
+    a.ix.split(id, i, j, k);
     const R h = cell_hmax(a.m, a.ndim, i, j, k);
     const double rho = a.rho[id];
     for (int q = 0; q < g.gp.m; ++q)
@@ -496,7 +501,8 @@ __global__ void __launch_bounds__(256) k_opacity_init(IArgs<R> a)
     const int N = n0 * n1 * a.n[2];
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= N) return;
-    const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    int i, j, k;
+    a.ix.split(id, i, j, k);
     const double T = gas_T(a.rho[id], a.mx[id], a.my[id], a.mz[id], a.Eg[id], a.k.gamma);
     const R rho = R(a.rho[id]);
     R kP, kR;
@@ -518,7 +524,8 @@ __global__ void __launch_bounds__(256) k_opacity_init_mlp(IArgs<R> a)
         const int id = blockIdx.x * blockDim.x + threadIdx.x;
         const bool live = id < N;
         const int idc = live ? id : N - 1;
-        const int i = idc % n0, j = (idc / n0) % n1, k = idc / (n0 * n1);
+        int i, j, k;
+        a.ix.split(idc, i, j, k);
         const double T = gas_T(a.rho[idc], a.mx[idc], a.my[idc], a.mz[idc], a.Eg[idc], a.k.gamma);
         const float rho = float(a.rho[idc]);
         float kP, kR;

@@ -427,6 +427,8 @@ m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1
     c->op.lr1 = lr1;
     c->op.lt0 = lt0;
     c->op.lt1 = lt1;
+    c->op.lr_inv = 1.0 / (lr1 - lr0);
+    c->op.lt_inv = 1.0 / (lt1 - lt0);
     c->op.lr_off = lr_off;
     c->op.lt_off = lt_off;
     c->op.tab_kP = c->table_dev;

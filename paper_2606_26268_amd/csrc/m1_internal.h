@@ -27,6 +27,48 @@ struct Metric {
     const R *cot_eff;   // cot(theta)_eff (per j), spherical only
 };
 
+// Unsigned division by a divisor fixed for the launch, with one multiply-high
+// instead of the vector ALU's long division sequence (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994,
+// Sect. 4): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+// t = mulhi(x, m) and x / d = (t + ((x - t) >> min(l, 1))) >> max(l - 1, 0),
+// exact for every 32-bit x and d >= 1.
+struct FastDiv {
+    unsigned d, m, s1, s2;
+    void set(unsigned dv)
+    {
+        unsigned l = 0;
+        while (l < 32 && (1ull << l) < dv) ++l;
+        d = dv;
+        m = unsigned(((1ull << 32) * ((1ull << l) - dv)) / dv + 1);
+        s1 = l ? 1 : 0;
+        s2 = l ? l - 1 : 0;
+    }
+    __device__ __forceinline__ unsigned div(unsigned x) const
+    {
+        const unsigned t = __umulhi(x, m);
+        return (t + ((x - t) >> s1)) >> s2;
+    }
+};
+
+// (i, j, k) of the cell with linear index id = (k n1 + j) n0 + i
+struct CellIndex {
+    FastDiv d0, d1;
+    void set(int n0, int n1)
+    {
+        d0.set(unsigned(n0));
+        d1.set(unsigned(n1));
+    }
+    __device__ __forceinline__ void split(int id, int &i, int &j, int &k) const
+    {
+        const unsigned q = d0.div(unsigned(id));
+        i = int(unsigned(id) - q * d0.d);
+        const unsigned kk = d1.div(q);
+        j = int(q - kk * d1.d);
+        k = int(kk);
+    }
+};
+
 enum OpacKind { OPK_CONST = 0, OPK_POWERLAW = 1, OPK_TABLE = 2, OPK_MLP = 3 };
 
 struct OpacityParams {
@@ -35,6 +77,7 @@ struct OpacityParams {
     double k0, rho0, alpha, T0, beta;           // power law
     int nr, nt;                                 // table
     double lr0, lr1, lt0, lt1, lr_off, lt_off;
+    double lr_inv, lt_inv;                      // 1 / (lr1 - lr0), 1 / (lt1 - lt0)
     const float *tab_kP, *tab_kR;               // device
     const float *mlp;                           // device, packed (see mlp.hip)
     double norm[4];

@@ -49,6 +49,14 @@ __device__ __forceinline__ float fast_tanh(float x)
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
 
+// kappa = 10^(y std + mean) from the normalised network output y, as
+// 2^((y std + mean) log2 10) on the hardware exp2 (the FP32 rounding of the
+// exponent dominates either way)
+__device__ __forceinline__ float net_kappa(float y, float sd, float mean)
+{
+    return __builtin_amdgcn_exp2f((y * sd + mean) * 3.3219280948873623f);
+}
+
 struct MlpWave {
     const float *p;
     bf16x8 w2h[2][4], w2l[2][4];
@@ -157,10 +165,15 @@ struct MlpWave {
     static __device__ __forceinline__ void inputs(const OpacityParams &op, float rho, float T, float &x0,
                                                   float &x1)
     {
-        float lr, lt;
-        table_coords<float>(op, rho, T, lr, lt);
-        x0 = 2.0f * (lr - float(op.lr0)) / float(op.lr1 - op.lr0) - 1.0f;
-        x1 = 2.0f * (lt - float(op.lt0)) / float(op.lt1 - op.lt0) - 1.0f;
+        // log10 through the hardware log2 (the network inputs carry FP32
+        // rounding in any case), clamped to the table axes
+        constexpr float LOG10_2 = 0.30102999566398120f;
+        float lr = __builtin_amdgcn_logf(rho) * LOG10_2 + float(op.lr_off);
+        float lt = __builtin_amdgcn_logf(T) * LOG10_2 + float(op.lt_off);
+        lr = __builtin_fminf(__builtin_fmaxf(lr, float(op.lr0)), float(op.lr1));
+        lt = __builtin_fminf(__builtin_fmaxf(lt, float(op.lt0)), float(op.lt1));
+        x0 = 2.0f * (lr - float(op.lr0)) * float(op.lr_inv) - 1.0f;
+        x1 = 2.0f * (lt - float(op.lt0)) * float(op.lt_inv) - 1.0f;
     }
 
     __device__ __forceinline__ void opacity(const OpacityParams &op, float rho, float T, int lane, float &kP,
@@ -169,8 +182,8 @@ struct MlpWave {
         float x0, x1, y0, y1;
         inputs(op, rho, T, x0, x1);
         forward(x0, x1, lane, y0, y1);
-        kP = exp10f(y0 * p[MLP_OFF_NORM + 1] + p[MLP_OFF_NORM + 0]);
-        kR = exp10f(y1 * p[MLP_OFF_NORM + 3] + p[MLP_OFF_NORM + 2]);
+        kP = net_kappa(y0, p[MLP_OFF_NORM + 1], p[MLP_OFF_NORM + 0]);
+        kR = net_kappa(y1, p[MLP_OFF_NORM + 3], p[MLP_OFF_NORM + 2]);
     }
 };
 
@@ -364,8 +377,8 @@ __device__ __forceinline__ void mlp_opacity_shared(const OpacityParams &op, cons
     float x0, x1, y0, y1;
     MlpWave::inputs(op, rho, T, x0, x1);
     mlp_forward_shared(p, sh, x0, x1, lane, y0, y1);
-    kP = exp10f(y0 * p[MLP_OFF_NORM + 1] + p[MLP_OFF_NORM + 0]);
-    kR = exp10f(y1 * p[MLP_OFF_NORM + 3] + p[MLP_OFF_NORM + 2]);
+    kP = net_kappa(y0, p[MLP_OFF_NORM + 1], p[MLP_OFF_NORM + 0]);
+    kR = net_kappa(y1, p[MLP_OFF_NORM + 3], p[MLP_OFF_NORM + 2]);
 }
 
 } // namespace m1

@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     __shared__ R sfy[4][TY + 1][TX];
     R *const sqf = &sq[0][0][0];
     const R *const stf = &st[0][0];
-    constexpr int QS = HY * HX, SS = NXS + NYS;
+    constexpr int QS = HY * HX;
 
     // consecutive logical tiles share an XCD (blocks are dealt to XCDs round-robin)
     const int per = (nblocks + 7) / 8;
