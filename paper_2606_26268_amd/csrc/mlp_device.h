@@ -249,7 +249,8 @@ __host__ __device__ constexpr int mlp_l1_unit(int mt, int r)
 struct MlpShared {
     bf16x8 w2[2][2][4][64];   // [hi, lo][mt][ks][lane], 16 KiB
     bf16x8 w1[2][64];         // layer-1 A operand: [mt][lane]
-    float4 ep[2][2][16];      // [g][mt][i]: scaled b2, W3[0], W3[1] of the slot's unit
+    float4 ep[2][2][16];      // [g][mt][i]: scaled b2, -2 W3[0], -2 W3[1] of the slot's unit
+    float w3sum[2];           // sum over units of W3[0], W3[1]
 };
 
 __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, int tid, int nthreads)
@@ -280,11 +281,27 @@ __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, in
         v.w = g ? bl : (bh | (bm << 16));
         sh.w1[mt][l] = __builtin_bit_cast(bf16x8, v);
     }
+    // the output layer takes h2 = 1 - 2 r (r = 1 / (1 + 2^z)) as
+    // sum W3 - 2 sum W3 r: weights -2 W3 per unit, the sum once per output
     for (int q = tid; q < 64; q += nthreads) {
         const int g = q >> 5, mt = (q >> 4) & 1, i = q & 15;
         const int u = MlpWave::unit(mt, i, g);
-        sh.ep[g][mt][i] = make_float4(MLP_TANH_SCALE * packed[MLP_OFF_B2 + u], packed[MLP_OFF_W3 + u],
-                                      packed[MLP_OFF_W3 + 64 + u], 0.0f);
+        sh.ep[g][mt][i] = make_float4(MLP_TANH_SCALE * packed[MLP_OFF_B2 + u], -2.0f * packed[MLP_OFF_W3 + u],
+                                      -2.0f * packed[MLP_OFF_W3 + 64 + u], 0.0f);
+    }
+    if (tid < 64) {
+        // fixed-order butterfly over the first wavefront: the same sums in
+        // every block
+        float s0 = packed[MLP_OFF_W3 + tid], s1 = packed[MLP_OFF_W3 + 64 + tid];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            s0 += __shfl_xor(s0, o);
+            s1 += __shfl_xor(s1, o);
+        }
+        if (tid == 0) {
+            sh.w3sum[0] = s0;
+            sh.w3sum[1] = s1;
+        }
     }
 }
 
@@ -355,9 +372,10 @@ __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShar
             const float4 w = sh.ep[g][mt][i];
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
-                const float h2 = tanh_scaled(__builtin_fmaf(acc[mt][nt][i], MLP_TANH_SCALE, w.x));
-                part[nt][0] = __builtin_fmaf(w.y, h2, part[nt][0]);
-                part[nt][1] = __builtin_fmaf(w.z, h2, part[nt][1]);
+                const float z = __builtin_fmaf(acc[mt][nt][i], MLP_TANH_SCALE, w.x);
+                const float r = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z));
+                part[nt][0] = __builtin_fmaf(w.y, r, part[nt][0]);
+                part[nt][1] = __builtin_fmaf(w.z, r, part[nt][1]);
             }
         }
     // the partner lane holds the other 32 units of the same samples
@@ -366,8 +384,8 @@ __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShar
     const float r0 = __shfl_xor(s0, 32), r1 = __shfl_xor(s1, 32);
     const float m0 = g ? part[1][0] : part[0][0];
     const float m1 = g ? part[1][1] : part[0][1];
-    y0 = m0 + r0 + p[MLP_OFF_B3] + p[MLP_OFF_WS] * x0 + p[MLP_OFF_WS + 1] * x1;
-    y1 = m1 + r1 + p[MLP_OFF_B3 + 1] + p[MLP_OFF_WS + 2] * x0 + p[MLP_OFF_WS + 3] * x1;
+    y0 = m0 + r0 + (p[MLP_OFF_B3] + sh.w3sum[0]) + p[MLP_OFF_WS] * x0 + p[MLP_OFF_WS + 1] * x1;
+    y1 = m1 + r1 + (p[MLP_OFF_B3 + 1] + sh.w3sum[1]) + p[MLP_OFF_WS + 2] * x0 + p[MLP_OFF_WS + 3] * x1;
 }
 
 __device__ __forceinline__ void mlp_opacity_shared(const OpacityParams &op, const MlpShared &sh, float rho, float T,
