@@ -92,11 +92,10 @@ def train_surrogate(m1, I, torch, solver, steps):
     return rep
 
 
-def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False, keep=False):
+def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False):
     """Returns dict with cells/s and per-kernel average durations (rk2: the
     second-order step, timed as a whole; its per-kernel fields are those of
-    the split step on the same state).  keep: also return the final state
-    (device copies in FP64) for comparing forms run on the same input."""
+    the split step on the same state)."""
     mlp = None
     if prob.opacity["kind"] == 3:
         # construct with the table, then train the surrogate in place
@@ -139,11 +138,23 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=F
     t_tr = sum(ev[k][0].elapsed_time(ev[k][1]) for k in range(K)) / K
     t_im = sum(ev[k][1].elapsed_time(ev[k][2]) for k in range(K)) / K
     d = s.diagnostics()
-    final = {k: v.detach().to(torch.float64).clone() for k, v in s.t.items() if k != "rho"} if keep else None
     s.close()
     n = prob.ncells
     return dict(cells_per_s=n * K / (ms * 1e-3), ms_per_step=ms / K, wall_s=wall,
-                transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp, state=final)
+                transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp)
+
+
+def fp32_deviation(m1, torch, prob, steps=100):
+    """Per-field deviation of the FP32 form from the FP64 form after the
+    same number of steps from the same input (field_errors)."""
+    st = {}
+    for prec in ("p64", "f32"):
+        s = m1.Solver(prob, precision=prec)
+        s.step(prob.dt, steps)
+        s.sync()
+        st[prec] = {k: v.detach().to(torch.float64).clone() for k, v in s.t.items() if k != "rho"}
+        s.close()
+    return field_errors(st["f32"], st["p64"])
 
 
 def field_errors(a, b):
@@ -238,18 +249,6 @@ def oracle_baseline(I, seconds_target=15.0, threads=None, shape=(96, 48, 96)):
                 sample=f"spherical recipe with MLP opacity on {shp} cells, {steps} steps, {t:.1f} s")
 
 
-def compare_pair(forms, name):
-    """Once both the FP32 and the FP64 run of a workload are done (same
-    input, same steps), store the FP32 result's per-field deviation from the
-    FP64 one with the FP32 form and release both final states."""
-    other = name.replace("f32", "p64") if "f32" in name else name.replace("p64", "f32")
-    if other not in forms:
-        return
-    f32, p64 = (name, other) if "f32" in name else (other, name)
-    forms[f32]["vs_p64"] = field_errors(forms[f32]["state"], forms[p64]["state"])
-    forms[f32]["state"] = forms[p64]["state"] = None
-
-
 def main():
     args = parse()
     if args.copy_calibration:
@@ -271,12 +270,15 @@ def main():
                                ("c1_p64_const", I.make_c1, "p64"), ("c1_f32_const", I.make_c1, "f32"),
                                ("c2_p64_const", I.make_c2, "p64"), ("c2_f32_const", I.make_c2, "f32")):
             log(f"form {name}")
-            forms[name] = time_form(m1, torch, mk(), prec, K, W, keep=True)
-            compare_pair(forms, name)
+            forms[name] = time_form(m1, torch, mk(), prec, K, W)
         for name, prec in (("c1_mg8_f32", "f32"), ("c1_mg8_p64", "p64")):
             log(f"form {name}")
-            forms[name] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), prec, K, W, keep=True)
-            compare_pair(forms, name)
+            forms[name] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), prec, K, W)
+        # accuracy of the FP32 forms: 100 steps against the FP64 form
+        for name, mk in (("c3_f32_table", I.make_c3), ("c1_f32_const", I.make_c1), ("c2_f32_const", I.make_c2),
+                         ("c1_mg8_f32", lambda: I.make_multigroup(8, (128, 128, 128)))):
+            log(f"fp32 deviation {name}")
+            forms[name]["vs_p64"] = fp32_deviation(m1, torch, mk())
         # the second-order step (two split steps and the average) on the table form
         log("form c3_f32_table_rk2")
         forms["c3_f32_table_rk2"] = time_form(m1, torch, I.make_c3(), "f32", K, W, rk2=True)
