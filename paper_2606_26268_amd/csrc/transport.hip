@@ -544,19 +544,23 @@ static int resident_blocks(const void *kern, int block)
     return cache[{kern, dev}] = per * cus;
 }
 
-// Tiled 3D launch.  The planes per block (z chunk) minimise the estimated
-// time rounds x (planes + 1): blocks run in rounds of the resident block
-// count, each chunk also pays about one plane of start-up (its first z face
-// and slopes), so a chunk that fills the last round evenly beats a smaller
-// one with a half-empty tail.
+// Tiled 3D launch.  The planes per block (z chunk) minimise rounds x
+// (planes + 1): blocks run in rounds of the resident block count, and each
+// chunk also pays about one plane of start-up (its first z face and slopes),
+// so a chunk that fills the last round evenly beats one that leaves a
+// mostly idle tail.  Chunks are kept to at most 16 planes: measured over the
+// 128^3, 256^3, 192x96x192 and eight-group workloads (chunks of 4 to 64
+// planes), the 28-64-plane chunks this cost picks without the cap were 4-6 %
+// slower than 16 (fewer blocks to balance, more halo misses in L2); with the
+// cap it lands on the fastest chunk measured or within 3 % of it.
 template <typename R, int GEOM, bool GENERAL>
 static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
 {
     const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
     const long slots = resident_blocks(reinterpret_cast<const void *>(&k_transport3d<R, GEOM, GENERAL>), NT);
-    int nz = 4;
+    int nz = 8;
     double best = 1e300;
-    for (int z = 2; z <= 64; ++z) {
+    for (int z = 2; z <= 16; ++z) {
         const long nb = long(tiles_x) * tiles_y * ((c->n[2] + z - 1) / z) * ngrp;
         const double cost = double((nb + slots - 1) / slots) * (z + 1);
         if (cost < best) {
