@@ -9,7 +9,7 @@ resident in device memory before timing starts.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--only]
 
 Prints one JSON line.  --only times the headline form alone (used under
-rocprofv3).  --gpus N > 1 is refused: this build runs on one GPU.
+rocprofv3).  --gpus N > 1 is refused: the implementation runs on one GPU.
 """
 from __future__ import annotations
 
@@ -255,7 +255,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2606_26268_amd import inputs as I

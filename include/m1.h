@@ -49,7 +49,7 @@ typedef enum {
     M1_ENOMEM = -2,   /* device or host allocation failed */
     M1_EDEVICE = -3,  /* HIP runtime error (launch or deferred kernel error) */
     M1_ESTATE = -4,   /* call out of order (e.g. implicit before explicit) */
-    M1_ENOTSUP = -5   /* valid request this build does not implement */
+    M1_ENOTSUP = -5   /* valid request the library does not implement */
 } m1_status;
 
 typedef enum { M1_CARTESIAN = 0, M1_CYLINDRICAL = 1, M1_SPHERICAL = 2 } m1_geometry;

@@ -87,7 +87,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+            raise ImportError(f"HIP library {LIB_PATH} is not built; run python -m paper_2606_26268_amd.build")
         L = C.CDLL(LIB_PATH)
         vp, dp = C.c_void_p, C.POINTER(C.c_double)
         sig = {
