@@ -256,11 +256,28 @@ __device__ __forceinline__ void face_fix(int recon, R U[4], const R C[4])
     for (int q = 0; q < 4; ++q) U[q] = C[q];
 }
 
+// the hardware's legacy multiply, 0 x anything = 0 (through the compiler's
+// intrinsic, so its scheduling and hazard rules apply)
+extern "C" __device__ float amdgcn_fmul_legacy(float, float) __asm("llvm.amdgcn.fmul.legacy");
+
+// van Leer limited slope without a branch, as
+// (dl |dr| + |dl| dr) / (|dl| + |dr|): the harmonic mean 2 dl dr / (dl + dr)
+// when the signs agree, zero when they differ or either is zero.  FP32 uses
+// the legacy multiply (0 x inf = 0), so dl = dr = 0 gives 0 without a select.
 template <typename R>
-__device__ __forceinline__ R vanleer_fast(R dl, R dr)
+__device__ __forceinline__ R vanleer_fast(R dl, R dr);
+template <>
+__device__ __forceinline__ float vanleer_fast<float>(float dl, float dr)
 {
-    const R p = dl * dr;
-    return p > R(0) ? (R(2) * p) * Num<R>::rcp(dl + dr) : R(0);
+    const float num = __builtin_fmaf(__builtin_fabsf(dl), dr, dl * __builtin_fabsf(dr));
+    return amdgcn_fmul_legacy(num, __builtin_amdgcn_rcpf(__builtin_fabsf(dl) + __builtin_fabsf(dr)));
+}
+template <>
+__device__ __forceinline__ double vanleer_fast<double>(double dl, double dr)
+{
+    const double den = __builtin_fabs(dl) + __builtin_fabs(dr);
+    const double num = __builtin_fma(__builtin_fabs(dl), dr, dl * __builtin_fabs(dr));
+    return den > 0.0 ? num * Num<double>::rcp(den) : 0.0;
 }
 
 // HLL flux c_hat Phi* at the face between donor cells b (left) and c (right)
