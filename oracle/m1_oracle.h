@@ -92,6 +92,8 @@ int m1o_mg_cell(int m, const double *Es, double Cv, double T, const double *kP, 
                 double c_hat, double c, double a, const double *b, double S, double *out);
 int m1o_run_mg(const m1o_problem *p, int m, const double *edges, const double *kPg, const double *kRg,
                double dt, int nsteps, double *const rad[], double *const gas[5], long long cnt[M1O_NCNT]);
+int m1o_run_mg_rk2(const m1o_problem *p, int m, const double *edges, const double *kPg, const double *kRg,
+                   double dt, int nsteps, double *const rad[], double *const gas[5], long long cnt[M1O_NCNT]);
 
 /* --- single-cell implicit solve (both algebraic forms) -------------------- */
 void m1o_implicit_cell(double Es, double Cv, double T, double kP, double rho, double dt,

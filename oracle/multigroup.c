@@ -189,3 +189,31 @@ int m1o_run_mg(const m1o_problem *p, int m, const double *edges, const double *k
     free(star);
     return 0;
 }
+
+/* Second-order Runge-Kutta stepping of the multigroup system, the scheme of
+ * the gray m1o_run_rk2 (Sect. 2.4: the transport + source sequence is the
+ * operator of every sub-step):
+ *   U1 = S(T(U^n)),  U2 = S(T(U1)),  U^{n+1} = (U^n + U2) / 2
+ * for every group's (E, F) and the gas (m, E_g); rho is frozen. */
+int m1o_run_mg_rk2(const m1o_problem *p, int m, const double *edges, const double *kPg, const double *kRg,
+                   double dt, int nsteps, double *const rad[], double *const gas[5], long long cnt[M1O_NCNT])
+{
+    if (m < 1 || m > M1O_MAX_GROUPS) return -1;
+    long N = (long)p->n[0] * p->n[1] * p->n[2];
+    int nf = 4 * m + 4;
+    double *save = malloc((size_t)nf * N * sizeof(double));
+    if (!save) return -1;
+    double *f[4 * M1O_MAX_GROUPS + 4];
+    for (int q = 0; q < 4 * m; ++q) f[q] = rad[q];
+    for (int q = 0; q < 4; ++q) f[4 * m + q] = gas[1 + q];     /* mx, my, mz, Eg */
+    for (int s = 0; s < nsteps; ++s) {
+        for (int q = 0; q < nf; ++q) memcpy(save + (long)q * N, f[q], N * sizeof(double));
+        if (m1o_run_mg(p, m, edges, kPg, kRg, dt, 2, rad, gas, cnt)) { free(save); return -1; }
+        for (int q = 0; q < nf; ++q) {
+#pragma omp parallel for schedule(static)
+            for (long id = 0; id < N; ++id) f[q][id] = 0.5 * (save[(long)q * N + id] + f[q][id]);
+        }
+    }
+    free(save);
+    return 0;
+}

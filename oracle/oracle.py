@@ -109,6 +109,8 @@ def lib():
         L.m1o_mg_cell.argtypes = [C.c_int, _dp] + [C.c_double] * 2 + [_dp] + [C.c_double] * 5 + [_dp, C.c_double, _dp]
         L.m1o_run_mg.restype = C.c_int
         L.m1o_run_mg.argtypes = [C.POINTER(Problem), C.c_int, _dp, _dp, _dp, C.c_double, C.c_int, pp, pp, cnt]
+        L.m1o_run_mg_rk2.restype = C.c_int
+        L.m1o_run_mg_rk2.argtypes = [C.POINTER(Problem), C.c_int, _dp, _dp, _dp, C.c_double, C.c_int, pp, pp, cnt]
         L.m1o_bf16_round.restype = C.c_double
         L.m1o_bf16_round.argtypes = [C.c_double]
         _lib = L
@@ -213,9 +215,10 @@ class Oracle:
             raise MemoryError("oracle run failed")
         return st, np.array(list(cnt))
 
-    def run_mg(self, fields, dt, nsteps):
+    def run_mg(self, fields, dt, nsteps, rk2=False):
         """Multigroup run (prob.groups = dict(edges, kP, kR)): fields E, Fx,
-        Fy, Fz have a leading group axis; returns (fields, counters)."""
+        Fy, Fz have a leading group axis; Euler split steps, or RK2 with
+        rk2=True; returns (fields, counters)."""
         gr = self.prob.groups
         m = len(gr["kP"])
         edges = np.ascontiguousarray(gr["edges"], dtype=np.float64).reshape(-1)
@@ -231,8 +234,8 @@ class Oracle:
                 rad.append(a)
         gas = self._arrs(st, ("rho", "mx", "my", "mz", "Eg"))
         cnt = (C.c_longlong * NCNT)()
-        rc = lib().m1o_run_mg(C.byref(self.P), m, _ptr(edges), _ptr(kP), _ptr(kR), dt, int(nsteps),
-                              self._pp(rad), self._pp(gas), cnt)
+        fn = lib().m1o_run_mg_rk2 if rk2 else lib().m1o_run_mg
+        rc = fn(C.byref(self.P), m, _ptr(edges), _ptr(kP), _ptr(kR), dt, int(nsteps), self._pp(rad), self._pp(gas), cnt)
         if rc != 0:
             raise RuntimeError("oracle multigroup run failed")
         return st, np.array(list(cnt))

@@ -165,3 +165,37 @@ def test_multigroup_absorption_only(orc):
         np.testing.assert_allclose(r["E"][g], t["E"][g] / (1 + p.dt * p.c_hat * kP * p.fields["rho"]), rtol=1e-14)
     ratio = p.c / p.c_hat
     np.testing.assert_allclose(r["Eg"] + ratio * r["E"].sum(axis=0), t["Eg"] + ratio * t["E"].sum(axis=0), rtol=1e-14)
+
+
+def test_one_group_rk2_equals_gray_rk2(orc):
+    """The multigroup second-order step with one group is the gray one."""
+    p = _mg_problem(1)
+    r, _ = orc.Oracle(p).run_mg(p.fields, p.dt, 4, rk2=True)
+    q = _mg_problem(1)
+    q.groups = None
+    for k in ("E", "Fx", "Fy", "Fz"):
+        q.fields[k] = np.ascontiguousarray(q.fields[k][0])
+    q.opacity = dict(kind=I.OPAC_CONSTANT, kP=p.groups["kP"][0], kR=p.groups["kR"][0], sigma=0.1)
+    g, _ = orc.Oracle(q).run(q.fields, q.dt, 4, rk2=True)
+    for k in ("E", "Fx", "Fy", "Fz"):
+        np.testing.assert_allclose(r[k][0], g[k], rtol=1e-12, atol=1e-14, err_msg=k)
+    for k in ("mx", "my", "mz", "Eg"):
+        np.testing.assert_allclose(r[k], g[k], rtol=1e-12, atol=1e-14, err_msg=k)
+
+
+def test_multigroup_rk2_conserves_and_differs_from_euler(orc):
+    """Each stage conserves E_g + (c / c_hat) sum_g E_g and m + sum_g F_g / c_hat
+    on a periodic box, so their average does; and the averaged step is not
+    the Euler step."""
+    p = _mg_problem(4)
+    r, _ = orc.Oracle(p).run_mg(p.fields, p.dt, 3, rk2=True)
+    ratio = p.c / p.c_hat
+    tot0 = p.fields["Eg"].sum() + ratio * p.fields["E"].sum()
+    tot1 = r["Eg"].sum() + ratio * r["E"].sum()
+    assert abs(tot1 - tot0) <= 1e-12 * tot0
+    for q, k in enumerate(("Fx", "Fy", "Fz")):
+        mom0 = p.fields["m" + k[1]].sum() + p.fields[k].sum() / p.c_hat
+        mom1 = r["m" + k[1]].sum() + r[k].sum() / p.c_hat
+        assert abs(mom1 - mom0) <= 1e-12 * (abs(p.fields[k]).sum() / p.c_hat)
+    e, _ = orc.Oracle(p).run_mg(p.fields, p.dt, 3)
+    assert np.abs(e["E"] - r["E"]).max() > 1e-9 * np.abs(r["E"]).max()
