@@ -282,6 +282,8 @@ def main():
         # the second-order step (two split steps and the average) on the table form
         log("form c3_f32_table_rk2")
         forms["c3_f32_table_rk2"] = time_form(m1, torch, I.make_c3(), "f32", K, W, rk2=True)
+        log("form c1_mg8_f32_rk2")
+        forms["c1_mg8_f32_rk2"] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), "f32", K, W, rk2=True)
         # the general transport kernel: Lax-Friedrichs flux with the simple
         # clip, reflective walls in x and irradiation heating
         log("form c1_f32_general")
@@ -321,12 +323,12 @@ def main():
         bps = algorithmic_bytes("transport", prec, kind) + algorithmic_bytes("implicit", prec, kind)
         if "general" in name:
             bps += 8                      # the irradiation heating array
-        if name.endswith("_rk2"):
-            bps *= 2                      # two split steps per second-order step
         if "_mg8_" in name:
             # per group: transport (E, F, tau in; E*, F* out) and E*, F* in / E, F out; gas once
             s = 4 if prec == "f32" else 8
             bps = 8 * (9 * s + 8 * s) + 72
+        if name.endswith("_rk2"):
+            bps *= 2                      # two split steps per second-order step
         out_forms[name] = dict(cells_per_s=r["cells_per_s"], ms_per_step=r["ms_per_step"],
                                transport_ms=r["transport_ms"], implicit_ms=r["implicit_ms"],
                                bytes_per_cell_step=bps,

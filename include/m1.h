@@ -255,8 +255,7 @@ m1_status m1_step_implicit(m1_ctx *ctx, double dt);
  * Fy, Fz hold m n0 n1 n2 values each, group-major (group g starts at
  * g n0 n1 n2).  The group opacities replace the gray opacity model.  m = 1
  * returns to the gray model.  1 <= m <= M1_MAX_GROUPS.  M1_ESTATE once a
- * state is bound; m1_step_rk2 and m1_opacity_eval return M1_ENOTSUP while
- * m > 1. */
+ * state is bound; m1_opacity_eval returns M1_ENOTSUP while m > 1. */
 #define M1_MAX_GROUPS 32
 m1_status m1_set_groups(m1_ctx *ctx, int m, const double *edges, const double *kP, const double *kR,
                         double sigma);
@@ -279,11 +278,12 @@ m1_status m1_set_irradiation(m1_ctx *ctx, const double *q);
 
 /* Second-order Runge-Kutta step of length dt built from the split step as in
  * Sect. 2.4 (every sub-step is transport then sources): U1 = S(T(U^n)),
- * U2 = S(T(U1)), U^{n+1} = (U^n + U2) / 2 for E, F, m and E_g (rho is
- * frozen); the opacity cache ends at the averaged gas state.  U1 lives in a
- * library buffer allocated on first use; the second stage writes the
- * average directly into the bound arrays.  Asynchronous.  M1_ESTATE if no
- * state is bound, M1_ENOTSUP for multigroup states. */
+ * U2 = S(T(U1)), U^{n+1} = (U^n + U2) / 2 for E, F (every group), m and
+ * E_g (rho is frozen); the opacity cache ends at the averaged gas state.
+ * U1 lives in a library buffer allocated on first use (4 m + 4 fields); the
+ * second stage writes the average directly into the bound arrays.
+ * Asynchronous.  M1_ESTATE if no state is bound, M1_ENOMEM if the buffer
+ * cannot be allocated. */
 m1_status m1_step_rk2(m1_ctx *ctx, double dt);
 
 /* Device pointers of the library's transported state E*, Fx*, Fy*, Fz*

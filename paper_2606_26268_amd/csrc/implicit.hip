@@ -244,6 +244,8 @@ static void fill_args(m1_ctx *c, IArgs<R> &a, const Metric<R> &met, double dt)
 // Stage 1 reads the caller's gas and writes U1 (radiation and gas) to the
 // save buffer; stage 2 reads U1's gas from there and writes (U^n + U2) / 2
 // into the caller's arrays, the opacity cache following the written state.
+// The buffer holds the four radiation fields of all groups (group-major, a
+// field every rk2_rad_bytes) and then the four gas fields.
 template <typename R>
 static void rk2_stage_args(m1_ctx *c, IArgs<R> &a, int stage)
 {
@@ -253,8 +255,8 @@ static void rk2_stage_args(m1_ctx *c, IArgs<R> &a, int stage)
     R *srad[4];
     double *sgas[4];
     for (int v = 0; v < 4; ++v) {
-        srad[v] = reinterpret_cast<R *>(sv + v * c->plane_bytes);
-        sgas[v] = reinterpret_cast<double *>(sv + 4 * c->plane_bytes) + v * N;
+        srad[v] = reinterpret_cast<R *>(sv + v * c->rk2_rad_bytes);
+        sgas[v] = reinterpret_cast<double *>(sv + 4 * c->rk2_rad_bytes) + v * N;
     }
     if (stage == 1) {
         a.E = srad[0];
@@ -383,7 +385,7 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
     if (id >= g.N) return;
     const int m = g.gp.m;
     const double rho = a.rho[id];
-    double mx = a.mx[id], my = a.my[id], mz = a.mz[id], Eg = a.Eg[id];
+    double mx = a.gin[0][id], my = a.gin[1][id], mz = a.gin[2][id], Eg = a.gin[3][id];
     const double inv_rho = 1.0 / rho;
     const double Cv = rho * a.k.inv_gm1;
     const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
@@ -430,19 +432,36 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
                 F1[2] *= sc;
                 atomicAdd(&a.cnt[2], 1ull);
             }
-            const R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
+            R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
             dE += double(E1r) - Es[q];
             for (int v = 0; v < 3; ++v) dF[v] += double(F1r[v]) - Fs[v];
-            a.E[q * g.N + id] = E1r;
-            a.Fx[q * g.N + id] = F1r[0];
-            a.Fy[q * g.N + id] = F1r[1];
-            a.Fz[q * g.N + id] = F1r[2];
+            const long o = q * g.N + id;
+            if (a.ravg[0]) {
+                // second-order step: (U^n + U2) / 2, the partner read before
+                // this cell is written
+                E1r = R(0.5 * (double(a.ravg[0][o]) + double(E1r)));
+                for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(a.ravg[1 + v][o]) + double(F1r[v])));
+            }
+            a.E[o] = E1r;
+            a.Fx[o] = F1r[0];
+            a.Fy[o] = F1r[1];
+            a.Fz[o] = F1r[2];
         }
     }
-    a.Eg[id] = Eg + S - a.k.c_ratio * dE;
-    a.mx[id] = mx - dF[0] * a.k.inv_ch;
-    a.my[id] = my - dF[1] * a.k.inv_ch;
-    a.mz[id] = mz - dF[2] * a.k.inv_ch;
+    Eg += S - a.k.c_ratio * dE;
+    mx -= dF[0] * a.k.inv_ch;
+    my -= dF[1] * a.k.inv_ch;
+    mz -= dF[2] * a.k.inv_ch;
+    if (a.ravg[0]) {
+        mx = 0.5 * (a.gavg[0][id] + mx);
+        my = 0.5 * (a.gavg[1][id] + my);
+        mz = 0.5 * (a.gavg[2][id] + mz);
+        Eg = 0.5 * (a.gavg[3][id] + Eg);
+    }
+    a.Eg[id] = Eg;
+    a.mx[id] = mx;
+    a.my[id] = my;
+    a.mz[id] = mz;
 }
 
 template <typename R>
@@ -457,10 +476,11 @@ static MgArgs<R> mg_args(m1_ctx *c)
 }
 
 template <typename R>
-static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met)
+static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met, int stage = 0)
 {
     IArgs<R> a;
     fill_args(c, a, met, dt);
+    rk2_stage_args(c, a, stage);
     const MgArgs<R> g = mg_args<R>(c);
     const dim3 grid(unsigned((g.N + 255) / 256)), block(256);
     if (g.gp.m <= 4)
@@ -476,6 +496,10 @@ static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met)
 
 hipError_t launch_implicit_rk2(m1_ctx *c, double dt, int stage)
 {
+    if (c->grp.m > 1) {
+        if (c->par.precision == M1_F32) return launch_i_mg<float>(c, dt, c->met32, stage);
+        return launch_i_mg<double>(c, dt, c->met64, stage);
+    }
     if (c->par.precision == M1_F32) return launch_i<float>(c, dt, c->met32, stage);
     return launch_i<double>(c, dt, c->met64, stage);
 }

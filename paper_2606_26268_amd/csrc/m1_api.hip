@@ -601,15 +601,17 @@ m1_status m1_step_rk2(m1_ctx *c, double dt)
     if (!c->bound) return fail(M1_ESTATE, "m1_step_rk2: no state bound");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(M1_EINVAL, "m1_step_rk2: dt must be > 0");
     if (!fixed_states_ready(c)) return fail(M1_ESTATE, "m1_step_rk2: a fixed boundary has no state");
-    if (c->grp.m > 1) return fail(M1_ENOTSUP, "m1_step_rk2: not available for multigroup states");
     const long N = ncells(c);
-    const size_t per = ((N * elem_size(c) + 255) / 256) * 256;
+    // U1: four radiation fields of all groups (group-major, as the bound
+    // arrays), then the gas (mx, my, mz, E_g)
+    const size_t per = ((size_t(c->grp.m) * N * elem_size(c) + 255) / 256) * 256;
     if (!c->rk2_save) {
         hipError_t e = hipMalloc(&c->rk2_save, 4 * per + 4 * N * sizeof(double));
         if (e != hipSuccess) {
             c->rk2_save = nullptr;
             return fail(M1_ENOMEM, "m1_step_rk2: save buffer allocation failed");
         }
+        c->rk2_rad_bytes = per;
     }
     // U1 = S(T(U^n)) into the save buffer (the caller's arrays keep U^n),
     // then U2 = S(T(U1)) written directly as (U^n + U2) / 2, the opacity

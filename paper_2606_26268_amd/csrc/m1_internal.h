@@ -133,7 +133,8 @@ struct m1_ctx {
     double *partials = nullptr;            // reduction scratch
     int npartial = 0;
     bool transported = false;
-    void *rk2_save = nullptr;              // state at t^n for m1_step_rk2
+    void *rk2_save = nullptr;              // first-stage state U1 of m1_step_rk2
+    size_t rk2_rad_bytes = 0;              // its per-field radiation stride (all groups)
 
     // opacity
     m1::OpacityParams op{};

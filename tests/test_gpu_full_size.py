@@ -1,8 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configurations the
 benchmark times, for the forms that the other GPU tests check on reduced
 grids only: the network-opacity form on the spherical 192x96x192 grid, the
-eight-group box at 128^3, the second-order step on the spherical grid with
-the table, and the general transport kernel (simple clip, Lax-Friedrichs
+eight-group box at 128^3 (split and second-order steps), the second-order
+step on the spherical grid with the table, and the general transport kernel (simple clip, Lax-Friedrichs
 flux, reflective walls, irradiation) on the 128^3 box."""
 import numpy as np
 import pytest
@@ -67,6 +67,24 @@ def test_multigroup_full_size_steps(orc, precision):
         assert_close(got, ref, tol, fields=MG_FIELDS, label="mg8 full p64")
     else:
         assert_close_f32(got, ref, fields=MG_FIELDS, label="mg8 full f32")
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_multigroup_rk2_full_size_step(orc, precision):
+    """One second-order step of the eight-group 128^3 box."""
+    from paper_2606_26268_amd import m1
+    p = I.make_multigroup(8, (128, 128, 128))
+    say(f"case multigroup rk2 8 groups 128^3 {precision}, 1 step")
+    ref, cnt = orc.Oracle(p).run_mg(p.fields, p.dt, 1, rk2=True)
+    s = m1.Solver(p, precision)
+    s.step(p.dt, 1, rk2=True)
+    got = s.state()
+    s.close()
+    if precision == "p64":
+        tol = TOL_P64 if cnt[1] + cnt[2] == 0 else TOL_P64_F1
+        assert_close(got, ref, tol, fields=MG_FIELDS, label="mg8 rk2 full p64")
+    else:
+        assert_close_f32(got, ref, fields=MG_FIELDS, label="mg8 rk2 full f32")
 
 
 @pytest.mark.parametrize("precision", ["p64", "f32"])

@@ -71,6 +71,27 @@ def test_multigroup_spherical_irradiated_absorbing(orc):
         assert_close(got, ref, tol, fields=FIELDS, label=f"mg-sph-{absorb}")
 
 
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_multigroup_rk2_parity(orc, precision):
+    """Second-order steps of the multigroup system (three groups, 20^3 box)
+    against the oracle's."""
+    p = I.make_multigroup(3, (20, 20, 20), seed=5)
+    p.c = 10 * p.c_hat
+    say(f"case multigroup rk2 m=3 {precision} 20^3")
+    ref, cnt = orc.Oracle(p).run_mg(p.fields, p.dt, 6, rk2=True)
+    from paper_2606_26268_amd import m1
+    s = m1.Solver(p, precision)
+    s.step(p.dt, 6, rk2=True)
+    got = s.state()
+    s.close()
+    if precision == "p64":
+        tol = TOL_P64 if cnt[1] + cnt[2] == 0 else TOL_P64_F1
+        say(f"  oracle f-clips after transport / implicit: {cnt[1]} / {cnt[2]}")
+        assert_close(got, ref, tol, fields=FIELDS, label="mg rk2")
+    else:
+        assert_close_f32(got, ref, fields=FIELDS, label="mg rk2", gas_scale=10.0)
+
+
 def test_multigroup_diagnostics_conserve_totals(orc):
     from paper_2606_26268_amd import m1
     p = I.make_multigroup(4, (24, 24, 24), seed=8)
@@ -96,7 +117,7 @@ def test_multigroup_errors():
         m1.m1_set_groups(s.ctx, 2, [1.0], [1.0, 1.0], [1.0, 1.0])
     assert e.value.status == m1.M1_ESTATE
     with pytest.raises(m1.M1Error) as e:
-        m1.m1_step_rk2(s.ctx, p.dt)
+        m1.m1_transported(s.ctx)
     assert e.value.status == m1.M1_ENOTSUP
     s.close()
     q = I.make_multigroup(3, (8, 8, 8), seed=1)
