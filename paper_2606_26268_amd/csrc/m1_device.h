@@ -232,6 +232,37 @@ __device__ __forceinline__ void ffix_sq(R U[4], const R C[4])
     }
 }
 
+// Donor-cell quantities of the f-preserving fix, |F_c|^2 and 1 / E_c,
+// computed once per cell and plane for all the faces the cell feeds.
+template <typename R>
+struct Centre {
+    R f2, ie;
+};
+template <typename R>
+__device__ __forceinline__ Centre<R> centre_of(const R C[4])
+{
+    return {C[1] * C[1] + C[2] * C[2] + C[3] * C[3], Num<R>::rcp(C[0])};
+}
+
+// ffix_sq with the donor cell's quantities supplied
+template <typename R>
+__device__ __forceinline__ void ffix_sq_c(R U[4], const R C[4], Centre<R> cc)
+{
+    if (U[0] > R(0)) {
+        const R Ff2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+        const R r = U[0] * cc.ie;
+        const bool keep = Ff2 <= U[0] * U[0] && Ff2 > cc.f2 * (r * r);
+        if (!keep) {
+            U[1] = C[1] * r;
+            U[2] = C[2] * r;
+            U[3] = C[3] * r;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) U[q] = C[q];
+    }
+}
+
 // Face treatment selected at run time: the f-preserving fix (default), the
 // "PLUTO" flat fallback or the simple clip (the alternatives of Sect. 2.5 and
 // the beam comparison of Sect. 3.2); both alternatives act only when
@@ -281,13 +312,15 @@ __device__ __forceinline__ double vanleer_fast<double>(double dl, double dr)
 }
 
 // HLL flux c_hat Phi* at the face between donor cells b (left) and c (right)
-// along d from their states and van Leer slopes (sb, sc; per unit length):
+// along d from their states, van Leer slopes (sb, sc; per unit length) and
+// f-fix quantities (cb, cc):
 // face states q_b + s_b hp_b and q_c - s_c hm_c, the face fix, both
 // closures and the optical-depth-limited HLL (or LF) flux.
 template <typename R>
 __device__ __forceinline__ void face_flux_s(int d, const R qb[4], const R qc[4], const R sb[4], const R sc[4],
-                                            R hpL, R hmR, R tauL, R tauR, R c_hat, R out[4],
-                                            int recon = M1_RECON_FPRESERVE, int riemann = M1_RIEMANN_HLL)
+                                            Centre<R> cb, Centre<R> cc, R hpL, R hmR, R tauL, R tauR, R c_hat,
+                                            R out[4], int recon = M1_RECON_FPRESERVE,
+                                            int riemann = M1_RIEMANN_HLL)
 {
     R UL[4], UR[4];
 #pragma unroll
@@ -295,8 +328,13 @@ __device__ __forceinline__ void face_flux_s(int d, const R qb[4], const R qc[4],
         UL[v] = qb[v] + sb[v] * hpL;
         UR[v] = qc[v] - sc[v] * hmR;
     }
-    face_fix(recon, UL, qb);
-    face_fix(recon, UR, qc);
+    if (recon == M1_RECON_FPRESERVE) {
+        ffix_sq_c(UL, qb, cb);
+        ffix_sq_c(UR, qc, cc);
+    } else {
+        face_fix(recon, UL, qb);
+        face_fix(recon, UR, qc);
+    }
     const Wave<R> wl = closure_wave_rt(UL[0], UL[1], UL[2], UL[3], d);
     const Wave<R> wr = closure_wave_rt(UR[0], UR[1], UR[2], UR[3], d);
     R lamL = wl.lm < wr.lm ? wl.lm : wr.lm;

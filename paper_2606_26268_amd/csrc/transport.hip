@@ -281,11 +281,13 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
     const int riemann = GENERAL ? a.riemann : int(M1_RIEMANN_HLL);
     __shared__ R sq[4][HY][HX];
     __shared__ R st[HY][HX];
+    __shared__ R scf[2][HY][HX];        // |F|^2 and 1 / E of the staged cells
     __shared__ R ss[4][NXS + NYS];      // slopes: x tasks, then y tasks
     __shared__ R sfx[4][TY][TX + 1];
     __shared__ R sfy[4][TY + 1][TX];
     R *const sqf = &sq[0][0][0];
     const R *const stf = &st[0][0];
+    const R *const scf2 = &scf[0][0][0], *const scie = &scf[1][0][0];
     constexpr int QS = HY * HX;
 
     // consecutive logical tiles share an XCD (blocks are dealt to XCDs round-robin)
@@ -417,6 +419,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
 
     // register window of the thread's column: planes k-1 .. k+2, z slope of plane k
     R W[4][4], T1, T2, Fzlo[4], Fzhi[4], Sz0[4];
+    Centre<R> C1;                       // f-fix quantities of plane k (W[1])
     {
         R Q0[4], Szm[4];
         load4(a, zlin(z0 - 2, col), Q0);
@@ -434,7 +437,9 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         T2 = a.tau[zlin(z0 + 1, col)];
         slopes4(Q0, W[0], W[1], wz[z0 + 1], wz[z0 + 2], Szm);
         slopes4(W[0], W[1], W[2], wz[z0 + 2], wz[z0 + 3], Sz0);
-        face_flux_s<R>(2, W[0], W[1], Szm, Sz0, hpz[z0 + 1], hmz[z0 + 2], Tm, T1, a.c_hat, Fzlo, recon, riemann);
+        C1 = centre_of(W[1]);
+        face_flux_s<R>(2, W[0], W[1], Szm, Sz0, centre_of(W[0]), C1, hpz[z0 + 1], hmz[z0 + 2], Tm, T1, a.c_hat,
+                       Fzlo, recon, riemann);
     }
 
     for (int k = z0; k < z1; ++k) {
@@ -452,10 +457,15 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
 #pragma unroll
         for (int v = 0; v < 4; ++v) sq[v][ly + 2][lx + 2] = W[1][v];
         st[ly + 2][lx + 2] = T1;
+        scf[0][ly + 2][lx + 2] = C1.f2;
+        scf[1][ly + 2][lx + 2] = C1.ie;
         if (tid < NHALO) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) sq[v][hy][hx] = Hq[v];
             st[hy][hx] = Ht;
+            const Centre<R> ch = centre_of(Hq);
+            scf[0][hy][hx] = ch.f2;
+            scf[1][hy][hx] = ch.ie;
         }
         __syncthreads();
 
@@ -494,14 +504,17 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
                 slb[v] = ss[v][sb];
                 slc[v] = ss[v][sb + sst];
             }
-            face_flux_s<R>(d, qb, qc, slb, slc, f_hp[p], f_hm[p], stf[b], stf[b + qst], a.c_hat, fl, recon, riemann);
+            face_flux_s<R>(d, qb, qc, slb, slc, Centre<R>{scf2[b], scie[b]}, Centre<R>{scf2[b + qst], scie[b + qst]},
+                           f_hp[p], f_hm[p], stf[b], stf[b + qst], a.c_hat, fl, recon, riemann);
             R *dst = d ? &sfy[0][0][0] : &sfx[0][0][0];
             const int fs = d ? (TY + 1) * TX : TY * (TX + 1);
 #pragma unroll
             for (int v = 0; v < 4; ++v) dst[v * fs + f_o[p]] = fl[v];
         }
         // z face above the plane from the register window
-        face_flux_s<R>(2, W[1], W[2], Sz0, Sz1, hpz[k + 2], hmz[k + 3], T1, T2, a.c_hat, Fzhi, recon, riemann);
+        const Centre<R> C2 = centre_of(W[2]);
+        face_flux_s<R>(2, W[1], W[2], Sz0, Sz1, C1, C2, hpz[k + 2], hmz[k + 3], T1, T2, a.c_hat, Fzhi, recon,
+                       riemann);
         __syncthreads();
 
         if (live) {
@@ -524,6 +537,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
         }
         T1 = T2;
         T2 = Tn;
+        C1 = C2;
     }
 }
 
