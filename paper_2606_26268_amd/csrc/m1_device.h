@@ -61,6 +61,12 @@ template <> struct Num<float> {
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 };
 
+// minimum / maximum as single instructions (finite arguments)
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
+
 // Closure quantities of one radiation state (E, F) seen from direction d:
 // lambda_-, lambda_+ (Sect. 2.5) and the flux (F_d, E D_{xd}, E D_{yd},
 // E D_{zd}) (Sect. 2.1, Eqs. rad1/rad2), all in units of c_hat.
@@ -186,7 +192,7 @@ __device__ __forceinline__ Wave<R> closure_wave_rt(R E, R Fx, R Fy, R Fz, int d)
     const R iE = Num<R>::rcp(E);
     R f2 = F2 * iE * iE;
     const bool clamped = f2 > R(1);
-    f2 = clamped ? R(1) : f2;
+    f2 = vmin(f2, R(1));
     const R s = Num<R>::sqrt_(R(4) - R(3) * f2);
     // Levermore: xi = (3 + 4 f^2) / (5 + 2 s) = (5 - 2 s) / 3, so
     // (1 - xi) / 2 = (s - 1) / 3 and (3 xi - 1) / 2 = 2 - s
@@ -194,8 +200,7 @@ __device__ __forceinline__ Wave<R> closure_wave_rt(R E, R Fx, R Fy, R Fz, int d)
     const R iF2 = iFn * iFn;
     const R Fd = d == 0 ? Fx : (d == 1 ? Fy : Fz);
     const R mu2 = Fd * Fd * iF2;
-    R z2 = (R(2) / R(3)) * (R(4) - R(3) * f2 - s) + R(2) * mu2 * (R(2) - f2 - s);
-    z2 = z2 < R(0) ? R(0) : z2;
+    const R z2 = vmax((R(2) / R(3)) * (R(4) - R(3) * f2 - s) + R(2) * mu2 * (R(2) - f2 - s), R(0));
     const R zeta = Num<R>::sqrt_(z2);
     const R fmu = clamped ? Fd * iFn : Fd * iE;
     const R is = Num<R>::rcp(s);
@@ -337,24 +342,20 @@ __device__ __forceinline__ void face_flux_s(int d, const R qb[4], const R qc[4],
     }
     const Wave<R> wl = closure_wave_rt(UL[0], UL[1], UL[2], UL[3], d);
     const Wave<R> wr = closure_wave_rt(UR[0], UR[1], UR[2], UR[3], d);
-    R lamL = wl.lm < wr.lm ? wl.lm : wr.lm;
-    R lamR = wl.lp > wr.lp ? wl.lp : wr.lp;
     const R tau = R(0.5) * (tauL + tauR);
-    if (tau > R(0)) {
-        const R lim = R(4) / R(3) * Num<R>::rcp(tau);
-        lamL = lamL < -lim ? -lim : lamL;
-        lamR = lamR > lim ? lim : lamR;
-    }
+    // optical-depth limit 4 / (3 tau) (none for tau = 0)
+    const R lim = tau > R(0) ? R(4) / R(3) * Num<R>::rcp(tau) : R(__builtin_inf());
+    const R lamL = vmax(vmin(wl.lm, wr.lm), -lim);
+    const R lamR = vmin(vmax(wl.lp, wr.lp), lim);
     if (riemann == M1_RIEMANN_LF) {
         // Lax-Friedrichs-Rusanov: largest limited speed magnitude
-        const R aL = lamL < R(0) ? -lamL : lamL, aR = lamR < R(0) ? -lamR : lamR;
-        const R sp = aL > aR ? aL : aR;
+        const R sp = vmax(__builtin_fabs(lamL), __builtin_fabs(lamR));
 #pragma unroll
         for (int q = 0; q < 4; ++q) out[q] = c_hat * (R(0.5) * (wl.phi[q] + wr.phi[q]) - R(0.5) * sp * (UR[q] - UL[q]));
         return;
     }
-    const R SL = lamL < R(0) ? lamL : R(0);
-    const R SR = lamR > R(0) ? lamR : R(0);
+    const R SL = vmin(lamL, R(0));
+    const R SR = vmax(lamR, R(0));
     if (SR > SL) {
         const R k = c_hat * Num<R>::rcp(SR - SL);
 #pragma unroll

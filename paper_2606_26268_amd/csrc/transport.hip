@@ -167,8 +167,7 @@ __device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], con
         // geometric sources from the cell-centre pressure tensor P = D E
         const R F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
         const R Fn = Num<R>::sqrt_(F2);
-        R f = Fn * Num<R>::rcp(U[0]);
-        f = f > R(1) ? R(1) : f;
+        const R f = vmin(Fn * Num<R>::rcp(U[0]), R(1));
         // Levermore: (1 - xi) / 2 = (s - 1) / 3, (3 xi - 1) / 2 = 2 - s
         const R s = Num<R>::sqrt_(R(4) - R(3) * f * f);
         const R inv = Fn > R(0) ? Num<R>::rcp(Fn) : R(0);
