@@ -202,7 +202,7 @@ __device__ __forceinline__ Wave<R> closure_wave_rt(R E, R Fx, R Fy, R Fz, int d)
     const R mu2 = Fd * Fd * iF2;
     const R z2 = vmax((R(2) / R(3)) * (R(4) - R(3) * f2 - s) + R(2) * mu2 * (R(2) - f2 - s), R(0));
     const R zeta = Num<R>::sqrt_(z2);
-    const R fmu = clamped ? Fd * iFn : Fd * iE;
+    const R fmu = Fd * (clamped ? iFn : iE);
     const R is = Num<R>::rcp(s);
     w.lm = (fmu - zeta) * is;
     w.lp = (fmu + zeta) * is;
@@ -250,22 +250,20 @@ __device__ __forceinline__ Centre<R> centre_of(const R C[4])
 }
 
 // ffix_sq with the donor cell's quantities supplied
+// (E_face <= 0 falls back to the centre state: ratio 1 and E_face = E_c).
 template <typename R>
 __device__ __forceinline__ void ffix_sq_c(R U[4], const R C[4], Centre<R> cc)
 {
-    if (U[0] > R(0)) {
-        const R Ff2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
-        const R r = U[0] * cc.ie;
-        const bool keep = Ff2 <= U[0] * U[0] && Ff2 > cc.f2 * (r * r);
-        if (!keep) {
-            U[1] = C[1] * r;
-            U[2] = C[2] * r;
-            U[3] = C[3] * r;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) U[q] = C[q];
+    const bool pos = U[0] > R(0);
+    const R Ff2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    const R r = pos ? U[0] * cc.ie : R(1);
+    const bool keep = pos && Ff2 <= U[0] * U[0] && Ff2 > cc.f2 * (r * r);
+    if (!keep) {
+        U[1] = C[1] * r;
+        U[2] = C[2] * r;
+        U[3] = C[3] * r;
     }
+    U[0] = pos ? U[0] : C[0];
 }
 
 // Face treatment selected at run time: the f-preserving fix (default), the

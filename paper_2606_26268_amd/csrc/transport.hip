@@ -157,31 +157,31 @@ __device__ __forceinline__ void ignorable_div(const TArgs<R> &a, const R U[4], R
 // U* = U - dt div(Phi) + dt c_hat S_geo(U), then E >= floor and f <= 1
 // (counted), stored to the transported state.
 template <typename R, int GEOM>
-__device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], const R acc[4], R ir, R ct, int id)
+__device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], Centre<R> cu, const R acc[4], R ir, R ct,
+                                            int id)
 {
     R Us[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) Us[v] = U[v] - a.dt * acc[v];
 
     if (GEOM != M1_CARTESIAN) {
-        // geometric sources from the cell-centre pressure tensor P = D E
-        const R F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
-        const R Fn = Num<R>::sqrt_(F2);
-        const R f = vmin(Fn * Num<R>::rcp(U[0]), R(1));
-        // Levermore: (1 - xi) / 2 = (s - 1) / 3, (3 xi - 1) / 2 = 2 - s
-        const R s = Num<R>::sqrt_(R(4) - R(3) * f * f);
-        const R inv = Fn > R(0) ? Num<R>::rcp(Fn) : R(0);
-        const R n_[3] = {U[1] * inv, U[2] * inv, U[3] * inv};
+        // geometric sources from the cell-centre pressure tensor
+        // P_ij = (2 - s) E F_i F_j / |F|^2 + delta_ij (s - 1) E / 3 (Levermore:
+        // (3 xi - 1) / 2 = 2 - s, (1 - xi) / 2 = (s - 1) / 3), from the cell's
+        // |F|^2 and 1 / E
+        const R f2 = vmin(cu.f2 * cu.ie * cu.ie, R(1));
+        const R s = Num<R>::sqrt_(R(4) - R(3) * f2);
+        const R iF2 = cu.f2 > R(0) ? Num<R>::rcp(cu.f2) : R(0);
         const R iso = (s - R(1)) * (R(1) / R(3)) * U[0];
-        const R an = (R(2) - s) * U[0];
+        const R an = (R(2) - s) * U[0] * iF2;
         const R k_ = a.dt * a.c_hat * ir;
         if (GEOM == M1_CYLINDRICAL) {           // (R, phi, z)
-            const R Ppp = an * n_[1] * n_[1] + iso, PRp = an * n_[0] * n_[1];
+            const R Ppp = an * U[2] * U[2] + iso, PRp = an * U[1] * U[2];
             Us[1] += k_ * Ppp;
             Us[2] -= k_ * PRp;
         } else {                                 // (r, theta, phi)
-            const R Ptt = an * n_[1] * n_[1] + iso, Ppp = an * n_[2] * n_[2] + iso;
-            const R Prt = an * n_[0] * n_[1], Prp = an * n_[0] * n_[2], Ptp = an * n_[1] * n_[2];
+            const R Ptt = an * U[2] * U[2] + iso, Ppp = an * U[3] * U[3] + iso;
+            const R Prt = an * U[1] * U[2], Prp = an * U[1] * U[3], Ptp = an * U[2] * U[3];
             Us[1] += k_ * (Ptt + Ppp);
             Us[2] += k_ * (ct * Ppp - Prt);
             Us[3] -= k_ * (Prp + ct * Ptp);
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
         ignorable_div<R, 2>(a, U, a.m.trA[2][i] * a.m.trB[2][j], acc);
     }
 
-    finish_cell<R, GEOM>(a, U, acc, GEOM == M1_CARTESIAN ? R(0) : a.m.inv_reff[i],
+    finish_cell<R, GEOM>(a, U, centre_of(U), acc, GEOM == M1_CARTESIAN ? R(0) : a.m.inv_reff[i],
                          GEOM == M1_SPHERICAL ? a.m.cot_eff[j] : R(0), id);
 }
 
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(NT) k_transport3d(TArgs<R> a, int nz_chunk, in
             for (int v = 0; v < 4; ++v)
                 acc[v] = (axh * sfx[v][ly][lx + 1] - axl * sfx[v][ly][lx]) +
                          (ayh * sfy[v][ly + 1][lx] - ayl * sfy[v][ly][lx]) + (azh * Fzhi[v] - azl * Fzlo[v]);
-            finish_cell<R, GEOM>(a, W[1], acc, ir, ct, (k * n1 + j) * n0 + i);
+            finish_cell<R, GEOM>(a, W[1], C1, acc, ir, ct, (k * n1 + j) * n0 + i);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
