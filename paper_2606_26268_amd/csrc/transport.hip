@@ -270,10 +270,11 @@ __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
     return tid - (nx - NT) < ny - NT ? NT + tid - (nx - NT) : -1;
 }
 
-// The FP32 general instantiation is held to three resident blocks per CU
-// (at most 168 VGPRs), which its register use just exceeds otherwise.
+// FP32 instantiations are held to four (default) and three (general)
+// resident blocks per CU, at most 128 and 168 VGPRs: the general one just
+// exceeds its bound otherwise, the default one fits exactly.
 template <typename R, int GEOM, bool GENERAL>
-__global__ void __launch_bounds__(NT, (GENERAL && sizeof(R) == 4) ? 3 : 1)
+__global__ void __launch_bounds__(NT, sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1)
     k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
 {
     select_group(a);
