@@ -6,10 +6,11 @@ implicit solve and the GPU-trained MLP opacity surrogate; the plain FP64
 form and the other forms are timed beside it.  Inputs are synthetic and
 resident in device memory before timing starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only | --form NAME]
 
-Prints one JSON line.  --only times the headline form alone (used under
-rocprofv3).  --gpus N > 1 is refused: the implementation runs on one GPU.
+Prints one JSON line.  --only times the headline form alone, --form NAME
+one of the other forms alone (both used under rocprofv3).  --gpus N > 1 is
+refused: the implementation runs on one GPU.
 """
 from __future__ import annotations
 
@@ -69,6 +70,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--only", action="store_true", help="time the headline form only")
+    ap.add_argument("--form", default=None, help="time one named form alone and print its figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--train-steps", type=int, default=None, help="override the Adam step count")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -249,6 +251,30 @@ def oracle_baseline(I, seconds_target=15.0, threads=None, shape=(96, 48, 96)):
                 sample=f"spherical recipe with MLP opacity on {shp} cells, {steps} steps, {t:.1f} s")
 
 
+def form_table(I):
+    """The forms timed beside the headline: name -> (problem maker,
+    precision, second-order step)."""
+    def mg8():
+        return I.make_multigroup(8, (128, 128, 128))
+
+    def general():
+        # the general transport kernel: Lax-Friedrichs flux with the simple
+        # clip, reflective walls in x and irradiation heating
+        pg = I.make_c1()
+        pg.recon, pg.riemann = 2, 1
+        pg.bc = [[I.REFLECT, I.REFLECT], [I.PERIODIC, I.PERIODIC], [I.PERIODIC, I.PERIODIC]]
+        pg.irr = pg.fields["rho"] * 0.1
+        return pg
+
+    return {"c3_f32_table": (I.make_c3, "f32", False), "c3_p64_table": (I.make_c3, "p64", False),
+            "c1_p64_const": (I.make_c1, "p64", False), "c1_f32_const": (I.make_c1, "f32", False),
+            "c2_p64_const": (I.make_c2, "p64", False), "c2_f32_const": (I.make_c2, "f32", False),
+            "c1_mg8_f32": (mg8, "f32", False), "c1_mg8_p64": (mg8, "p64", False),
+            # the second-order step (two split steps and the average)
+            "c3_f32_table_rk2": (I.make_c3, "f32", True), "c1_mg8_f32_rk2": (mg8, "f32", True),
+            "c1_f32_general": (general, "f32", False)}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -262,36 +288,29 @@ def main():
     from paper_2606_26268_amd import m1
     K, W = args.steps, args.warmup
 
+    table = form_table(I)
+    if args.form:
+        # one named form alone (for profiling); prints its own figures
+        if args.form not in table:
+            print(json.dumps({"error": f"unknown form {args.form}", "forms": sorted(table)}))
+            sys.exit(2)
+        mk, prec, rk2 = table[args.form]
+        r = time_form(m1, torch, mk(), prec, K, W, rk2=rk2)
+        print(json.dumps({"form": args.form, "cells_per_s": r["cells_per_s"], "ms_per_step": r["ms_per_step"],
+                          "transport_ms": r["transport_ms"], "implicit_ms": r["implicit_ms"]}))
+        return
+
     log("headline: spherical 192x96x192, f32 transport + f64 implicit + MLP opacity")
     head = time_form(m1, torch, I.make_c4(), "f32", K, W, args.train_steps, I)
     forms = {"c4_f32_mlp": head}
     if not args.only:
-        for name, mk, prec in (("c3_f32_table", I.make_c3, "f32"), ("c3_p64_table", I.make_c3, "p64"),
-                               ("c1_p64_const", I.make_c1, "p64"), ("c1_f32_const", I.make_c1, "f32"),
-                               ("c2_p64_const", I.make_c2, "p64"), ("c2_f32_const", I.make_c2, "f32")):
+        for name, (mk, prec, rk2) in table.items():
             log(f"form {name}")
-            forms[name] = time_form(m1, torch, mk(), prec, K, W)
-        for name, prec in (("c1_mg8_f32", "f32"), ("c1_mg8_p64", "p64")):
-            log(f"form {name}")
-            forms[name] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), prec, K, W)
+            forms[name] = time_form(m1, torch, mk(), prec, K, W, rk2=rk2)
         # accuracy of the FP32 forms: 100 steps against the FP64 form
-        for name, mk in (("c3_f32_table", I.make_c3), ("c1_f32_const", I.make_c1), ("c2_f32_const", I.make_c2),
-                         ("c1_mg8_f32", lambda: I.make_multigroup(8, (128, 128, 128)))):
+        for name in ("c3_f32_table", "c1_f32_const", "c2_f32_const", "c1_mg8_f32"):
             log(f"fp32 deviation {name}")
-            forms[name]["vs_p64"] = fp32_deviation(m1, torch, mk())
-        # the second-order step (two split steps and the average) on the table form
-        log("form c3_f32_table_rk2")
-        forms["c3_f32_table_rk2"] = time_form(m1, torch, I.make_c3(), "f32", K, W, rk2=True)
-        log("form c1_mg8_f32_rk2")
-        forms["c1_mg8_f32_rk2"] = time_form(m1, torch, I.make_multigroup(8, (128, 128, 128)), "f32", K, W, rk2=True)
-        # the general transport kernel: Lax-Friedrichs flux with the simple
-        # clip, reflective walls in x and irradiation heating
-        log("form c1_f32_general")
-        pg = I.make_c1()
-        pg.recon, pg.riemann = 2, 1
-        pg.bc = [[I.REFLECT, I.REFLECT], [I.PERIODIC, I.PERIODIC], [I.PERIODIC, I.PERIODIC]]
-        pg.irr = pg.fields["rho"] * 0.1
-        forms["c1_f32_general"] = time_form(m1, torch, pg, "f32", K, W)
+            forms[name]["vs_p64"] = fp32_deviation(m1, torch, table[name][0]())
 
     ncell = 192 * 96 * 192
     # HBM fractions are also given against what a plain copy reaches here
