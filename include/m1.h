@@ -170,8 +170,9 @@ m1_status m1_params_default(double c_hat, m1_params *p);
 /* Create a context for grid g (copied) in geometry geom with reduced speed
  * of light c_hat (> 0).  p may be NULL (defaults).  Uploads the separable
  * metric arrays of the grid.  Errors: M1_EINVAL (ndim outside 1..3,
- * n[d] < 1, n[d] != 1 for d >= ndim, non-increasing faces, negative radius,
- * theta outside [0, pi], c_hat <= 0, unknown enum), M1_ENOMEM, M1_EDEVICE. */
+ * n[d] < 1, n[d] != 1 for d >= ndim, more than 2^31 - 2^16 cells,
+ * non-increasing faces, negative radius, theta outside [0, pi],
+ * c_hat <= 0, unknown enum), M1_ENOMEM, M1_EDEVICE. */
 m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_params *p,
                     m1_ctx **out);
 

@@ -26,11 +26,12 @@ __global__ void __launch_bounds__(256) k_diag_partial(DArgs<R> a)
 {
     __shared__ double sh[DIAG_VALUES][256];
     const int n0 = a.n[0], n1 = a.n[1];
-    const int N = n0 * n1 * a.n[2];
+    const long N = long(n0) * n1 * a.n[2];
     double acc[5] = {0, 0, 0, 0, 0};
     double mn = 1.0e300, mx = 0.0;
-    for (int id = blockIdx.x * 256 + threadIdx.x; id < N; id += gridDim.x * 256) {
-        const int i = id % n0, j = (id / n0) % n1, k = id / (n0 * n1);
+    // 64-bit stride: the index past the last cell may exceed 2^31
+    for (long id = long(blockIdx.x) * 256 + threadIdx.x; id < N; id += long(gridDim.x) * 256) {
+        const int i = int(id % n0), j = int((id / n0) % n1), k = int(id / (long(n0) * n1));
         const double V = a.vol[0][i] * a.vol[1][j] * a.vol[2][k];
         double Et = 0.0, Ft[3] = {0.0, 0.0, 0.0};
         for (int g = 0; g < a.groups; ++g) {

@@ -269,7 +269,9 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
                 return fail(M1_EINVAL, "m1_create: faces must be strictly increasing");
         total *= g->n[d];
     }
-    if (total >= (1L << 31)) return fail(M1_EINVAL, "m1_create: too many cells");
+    // cell indices are 32-bit in the kernels, including the padded last
+    // block of a launch
+    if (total > (1L << 31) - (1L << 16)) return fail(M1_EINVAL, "m1_create: too many cells (at most 2^31 - 2^16)");
     if (geom != M1_CARTESIAN && g->faces[0][0] < 0.0)
         return fail(M1_EINVAL, "m1_create: negative radius");
     if (geom == M1_SPHERICAL && (g->faces[1][0] < 0.0 || g->faces[1][g->n[1]] > M_PI + 1e-12))

@@ -311,7 +311,8 @@ GAS = ("rho", "mx", "my", "mz", "Eg")
 class Solver:
     """Device state of one problem plus a library context.
 
-    prob: ``inputs.Problem``; precision: "p64" or "f32"; mlp: optional
+    prob: ``inputs.Problem`` (fields as numpy arrays, or device tensors that
+    are used in place); precision: "p64" or "f32"; mlp: optional
     dict(theta=float32[4486], norm=4 floats) for the MLP opacity kind.
     """
 
@@ -321,10 +322,18 @@ class Solver:
         self.precision = M1_F32 if precision == "f32" else M1_P64
         rdt = torch.float32 if self.precision == M1_F32 else torch.float64
         self.t = {}
+
+        def dev(a, dt):
+            # numpy arrays are copied to the device; device tensors are taken
+            # as they are (converted only if the dtype differs)
+            if isinstance(a, torch.Tensor):
+                return a.to(self.device, dt).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(a)).to(self.device, dt).contiguous()
+
         for k in RAD:
-            self.t[k] = torch.from_numpy(np.ascontiguousarray(prob.fields[k])).to(self.device, rdt).contiguous()
+            self.t[k] = dev(prob.fields[k], rdt)
         for k in GAS:
-            self.t[k] = torch.from_numpy(np.ascontiguousarray(prob.fields[k])).to(self.device, torch.float64).contiguous()
+            self.t[k] = dev(prob.fields[k], torch.float64)
         par = m1_params_default(prob.c_hat)
         par.c, par.a_rad, par.gamma = prob.c, prob.a_rad, prob.gamma
         par.precision, par.e_floor = self.precision, prob.e_floor
