@@ -70,7 +70,7 @@ __device__ __forceinline__ double gas_T_r(double inv_rho, double mx, double my, 
 // about 1 ulp): 1/rho, the determinant, the flux damping factor and the
 // optical depth per length.
 template <typename R, bool CONST_OPAC>
-__device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i, int j, int k)
+__device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, R hmax)
 {
     const double rho = a.rho[id];
     double mx = a.gin[0][id], my = a.gin[1][id], mz = a.gin[2][id], Eg = a.gin[3][id];
@@ -83,7 +83,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
         rchi = rho * (a.op.kR + a.op.sigma);
     } else {
         rkP = double(a.rkp[id]);
-        rchi = double(a.tau[id]) * Num<double>::rcp(double(cell_hmax(a.m, a.ndim, i, j, k)));
+        rchi = double(a.tau[id]) * Num<double>::rcp(double(hmax));
     }
     const double Es = double(a.Es[id]);
     const double Fs[3] = {double(a.Fxs[id]), double(a.Fys[id]), double(a.Fzs[id])};
@@ -105,7 +105,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, int i
         E1 = (Cv * (Es + gr * aT4) + 4.0 * aT3 * (g * Es + gr * S)) * Num<double>::rcp(det);
     const double inv_damp = Num<double>::rcp(1.0 + a.k.dt_ch * rchi);   // Eq. source_discrete2
     double F1[3] = {Fs[0] * inv_damp, Fs[1] * inv_damp, Fs[2] * inv_damp};
-    const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
+    const double Fn = Num<double>::sqrt_(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
     if (Fn > E1) {
         const double s = E1 / Fn;
         F1[0] *= s;
@@ -150,13 +150,15 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
     if (id >= N) return;
     int i, j, k;
     a.ix.split(id, i, j, k);
-    const double T1 = implicit_cell<R, OPK == OPK_CONST>(a, id, i, j, k);
+    // the cell extent serves both the optical depth read and the one written
+    const R hm = OPK == OPK_CONST ? R(0) : cell_hmax(a.m, a.ndim, i, j, k);
+    const double T1 = implicit_cell<R, OPK == OPK_CONST>(a, id, hm);
     if (OPK != OPK_CONST) {
         const R rho = R(a.rho[id]);
         R kP, kR;
         opacity_analytic<R, OPK>(a.op, rho, R(T1), kP, kR);
         a.rkp[id] = rho * kP;
-        a.tau[id] = rho * (kR + R(a.op.sigma)) * cell_hmax(a.m, a.ndim, i, j, k);
+        a.tau[id] = rho * (kR + R(a.op.sigma)) * hm;
     }
 }
 
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
 // dead during the staging, which keeps the kernel within the scalar register
 // file (staged first, the pointers were spilled to vector lanes).
 template <typename R>
-__global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
+__global__ void __launch_bounds__(256, 4) k_implicit_mlp(IArgs<R> a)
 {
     const int n0 = a.n[0], n1 = a.n[1];
     const int N = n0 * n1 * a.n[2];
@@ -179,8 +181,9 @@ __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
         const int idc = live ? id : N - 1;
         int i, j, k;
         a.ix.split(idc, i, j, k);
+        const R hm = cell_hmax(a.m, a.ndim, i, j, k);
         double T1 = 1.0;
-        if (live) T1 = implicit_cell<R, false>(a, id, i, j, k);
+        if (live) T1 = implicit_cell<R, false>(a, id, hm);
         const float rho = float(a.rho[idc]);
         mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
         __syncthreads();
@@ -188,7 +191,7 @@ __global__ void __launch_bounds__(256) k_implicit_mlp(IArgs<R> a)
         mlp_opacity_shared(a.op, sh, rho, float(T1), lane, kP, kR);
         if (live) {
             a.rkp[id] = R(rho * kP);
-            a.tau[id] = R(rho * (kR + float(a.op.sigma))) * cell_hmax(a.m, a.ndim, i, j, k);
+            a.tau[id] = R(rho * (kR + float(a.op.sigma))) * hm;
         }
     }
 }
@@ -424,7 +427,7 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
                 Fs[v] = double(reinterpret_cast<const R *>(g.star + (4 * q + 1 + v) * g.plane)[id]);
                 F1[v] = Fs[v] * inv_damp;
             }
-            const double Fn = sqrt(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
+            const double Fn = Num<double>::sqrt_(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
             if (Fn > E1) {
                 const double sc = E1 / Fn;
                 F1[0] *= sc;
