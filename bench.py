@@ -109,7 +109,7 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=F
         log(f"  surrogate trained: {rep}")
         mlp = rep
     else:
-        s = m1.Solver(prob, precision=precision)
+        s = m1.Solver(prob, precision=precision, second_order=rk2)
     dt = prob.dt
     stream = s.stream
     for _ in range(W):

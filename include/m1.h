@@ -92,7 +92,10 @@ typedef struct {
  * absorb_only  0 (default): the full radiation-matter system of
  *         Eq. implicit_matrix; 1: absorption without emission,
  *         E' = E* / (1 + dt c_hat kappa_P rho) (shadow test, Sect. 3.3), the
- *         absorbed energy going to the gas */
+ *         absorbed energy going to the gas
+ * second_order  0 (default) or 1: m1_bind_state also allocates the buffer
+ *         of m1_step_rk2 (the first-stage state, 4 m + 4 fields), so that no
+ *         step call allocates */
 typedef struct {
     double c;
     double a_rad;
@@ -102,6 +105,7 @@ typedef struct {
     int recon;
     int riemann;
     int absorb_only;
+    int second_order;
 } m1_params;
 
 /* Caller-owned device state bound to a context (see conventions). */
@@ -281,10 +285,11 @@ m1_status m1_set_irradiation(m1_ctx *ctx, const double *q);
  * Sect. 2.4 (every sub-step is transport then sources): U1 = S(T(U^n)),
  * U2 = S(T(U1)), U^{n+1} = (U^n + U2) / 2 for E, F (every group), m and
  * E_g (rho is frozen); the opacity cache ends at the averaged gas state.
- * U1 lives in a library buffer allocated on first use (4 m + 4 fields); the
- * second stage writes the average directly into the bound arrays.
- * Asynchronous.  M1_ESTATE if no state is bound, M1_ENOMEM if the buffer
- * cannot be allocated. */
+ * U1 lives in a library buffer (4 m + 4 fields) that m1_bind_state
+ * allocates when the context was created with m1_params.second_order = 1;
+ * the second stage writes the average directly into the bound arrays.
+ * Asynchronous.  M1_ESTATE if no state is bound or the context was created
+ * without second_order. */
 m1_status m1_step_rk2(m1_ctx *ctx, double dt);
 
 /* Device pointers of the library's transported state E*, Fx*, Fy*, Fz*

@@ -242,6 +242,7 @@ m1_status m1_params_default(double c_hat, m1_params *p)
     p->recon = M1_RECON_FPRESERVE;
     p->riemann = M1_RIEMANN_HLL;
     p->absorb_only = 0;
+    p->second_order = 0;
     return M1_OK;
 }
 
@@ -286,6 +287,8 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
         return fail(M1_EINVAL, "m1_create: unknown reconstruction or Riemann solver");
     if (par.absorb_only != 0 && par.absorb_only != 1)
         return fail(M1_EINVAL, "m1_create: absorb_only must be 0 or 1");
+    if (par.second_order != 0 && par.second_order != 1)
+        return fail(M1_EINVAL, "m1_create: second_order must be 0 or 1");
     if (!(par.c > 0.0) || !(par.gamma > 1.0) || !(par.a_rad > 0.0))
         return fail(M1_EINVAL, "m1_create: c, a_rad must be > 0 and gamma > 1");
     m1_ctx *c = new (std::nothrow) m1_ctx();
@@ -354,6 +357,21 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     }
     hipError_t e = hipMalloc(&c->scratch, bytes);
     if (e != hipSuccess) return fail(M1_ENOMEM, "m1_bind_state: scratch allocation failed");
+    if (c->rk2_save) {
+        hipFree(c->rk2_save);
+        c->rk2_save = nullptr;
+    }
+    if (c->par.second_order) {
+        // the first-stage state of m1_step_rk2: the four radiation fields of
+        // all groups (group-major, as the bound arrays), then mx, my, mz, E_g
+        const size_t rad = ((size_t(G) * N * es + 255) / 256) * 256;
+        e = hipMalloc(&c->rk2_save, 4 * rad + 4 * N * sizeof(double));
+        if (e != hipSuccess) {
+            c->rk2_save = nullptr;
+            return fail(M1_ENOMEM, "m1_bind_state: second-order buffer allocation failed");
+        }
+        c->rk2_rad_bytes = rad;
+    }
     unsigned char *b = static_cast<unsigned char *>(c->scratch);
     // layout: star (group g, field v) at (4 g + v) per, tau of group g at
     // (4 G + g) per, rho kappa_P at 5 G per
@@ -603,18 +621,9 @@ m1_status m1_step_rk2(m1_ctx *c, double dt)
     if (!c->bound) return fail(M1_ESTATE, "m1_step_rk2: no state bound");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(M1_EINVAL, "m1_step_rk2: dt must be > 0");
     if (!fixed_states_ready(c)) return fail(M1_ESTATE, "m1_step_rk2: a fixed boundary has no state");
-    const long N = ncells(c);
-    // U1: four radiation fields of all groups (group-major, as the bound
-    // arrays), then the gas (mx, my, mz, E_g)
-    const size_t per = ((size_t(c->grp.m) * N * elem_size(c) + 255) / 256) * 256;
-    if (!c->rk2_save) {
-        hipError_t e = hipMalloc(&c->rk2_save, 4 * per + 4 * N * sizeof(double));
-        if (e != hipSuccess) {
-            c->rk2_save = nullptr;
-            return fail(M1_ENOMEM, "m1_step_rk2: save buffer allocation failed");
-        }
-        c->rk2_rad_bytes = per;
-    }
+    if (!c->rk2_save)
+        return fail(M1_ESTATE, "m1_step_rk2: create the context with m1_params.second_order = 1");
+    const size_t per = c->rk2_rad_bytes;
     // U1 = S(T(U^n)) into the save buffer (the caller's arrays keep U^n),
     // then U2 = S(T(U1)) written directly as (U^n + U2) / 2, the opacity
     // cache following each stage's written state

@@ -43,7 +43,8 @@ class m1_grid(C.Structure):
 class m1_params(C.Structure):
     _fields_ = [("c", C.c_double), ("a_rad", C.c_double), ("gamma", C.c_double),
                 ("precision", C.c_int), ("e_floor", C.c_double), ("recon", C.c_int), ("riemann", C.c_int),
-                ("absorb_only", C.c_int)]
+                ("absorb_only", C.c_int),
+                ("second_order", C.c_int)]
 
 
 class m1_fields(C.Structure):
@@ -313,10 +314,12 @@ class Solver:
 
     prob: ``inputs.Problem`` (fields as numpy arrays, or device tensors that
     are used in place); precision: "p64" or "f32"; mlp: optional
-    dict(theta=float32[4486], norm=4 floats) for the MLP opacity kind.
+    dict(theta=float32[4486], norm=4 floats) for the MLP opacity kind;
+    second_order: allocate the buffer of the second-order step at binding
+    (needed by step(..., rk2=True)).
     """
 
-    def __init__(self, prob, precision="p64", device="cuda:0", mlp=None, stream=None):
+    def __init__(self, prob, precision="p64", device="cuda:0", mlp=None, stream=None, second_order=False):
         self.prob = prob
         self.device = torch.device(device)
         self.precision = M1_F32 if precision == "f32" else M1_P64
@@ -339,6 +342,7 @@ class Solver:
         par.precision, par.e_floor = self.precision, prob.e_floor
         par.recon, par.riemann = getattr(prob, "recon", 0), getattr(prob, "riemann", 0)
         par.absorb_only = int(getattr(prob, "absorb_only", 0))
+        par.second_order = int(bool(second_order))
         self.ctx = m1_create(prob.ndim, prob.n, prob.faces, prob.bc, prob.geometry, prob.c_hat, par)
         bs = getattr(prob, "bc_state", None)
         if bs is not None:

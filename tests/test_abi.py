@@ -33,3 +33,13 @@ def test_library_exports_every_declared_symbol():
 def test_binding_covers_header():
     from paper_2606_26268_amd import m1
     assert sorted(m1.EXPORTS) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_params_layout_matches_the_header():
+    """m1_params_default (host code, no GPU) fills the binding's structure
+    with the documented defaults: the field offsets agree with m1.h."""
+    from paper_2606_26268_amd import m1
+    p = m1.m1_params_default(2.5)
+    assert (p.c, p.a_rad, p.gamma, p.e_floor) == (2.5, 1.0, 5.0 / 3.0, 1e-30)
+    assert (p.precision, p.recon, p.riemann, p.absorb_only, p.second_order) == (m1.M1_P64, 0, 0, 0, 0)

@@ -76,7 +76,7 @@ def test_multigroup_rk2_full_size_step(orc, precision):
     p = I.make_multigroup(8, (128, 128, 128))
     say(f"case multigroup rk2 8 groups 128^3 {precision}, 1 step")
     ref, cnt = orc.Oracle(p).run_mg(p.fields, p.dt, 1, rk2=True)
-    s = m1.Solver(p, precision)
+    s = m1.Solver(p, precision, second_order=True)
     s.step(p.dt, 1, rk2=True)
     got = s.state()
     s.close()
@@ -95,7 +95,7 @@ def test_rk2_full_size_steps(orc, precision):
     p = I.make_c3()
     say(f"case rk2 c3 full size {precision}, 2 steps")
     ref, _ = orc.Oracle(p).run(p.fields, p.dt, 2, rk2=True)
-    s = m1.Solver(p, precision)
+    s = m1.Solver(p, precision, second_order=True)
     s.step(p.dt, 2, rk2=True)
     got = s.state()
     s.close()

@@ -80,7 +80,7 @@ def test_multigroup_rk2_parity(orc, precision):
     say(f"case multigroup rk2 m=3 {precision} 20^3")
     ref, cnt = orc.Oracle(p).run_mg(p.fields, p.dt, 6, rk2=True)
     from paper_2606_26268_amd import m1
-    s = m1.Solver(p, precision)
+    s = m1.Solver(p, precision, second_order=True)
     s.step(p.dt, 6, rk2=True)
     got = s.state()
     s.close()

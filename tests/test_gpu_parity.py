@@ -242,7 +242,7 @@ def test_rk2_steps(orc, precision):
     dt = o.max_dt(0.4)
     ref, cnt = o.run(p.fields, dt, 8, rk2=True)
     from paper_2606_26268_amd import m1
-    s = m1.Solver(p, precision)
+    s = m1.Solver(p, precision, second_order=True)
     s.step(dt, 8, rk2=True)
     got = s.state()
     s.close()
@@ -250,6 +250,18 @@ def test_rk2_steps(orc, precision):
         assert_close(got, ref, TOL_P64, label="rk2 p64")
     else:
         assert_close_f32(got, ref, label="rk2 f32")
+
+
+def test_rk2_needs_second_order():
+    """Without m1_params.second_order the context holds no buffer for the
+    second-order step, and the step is refused instead of allocating."""
+    from paper_2606_26268_amd import m1
+    p = _problem(I.CARTESIAN, (16, 8, 4), 3, seed=3)
+    s = m1.Solver(p, "p64")
+    with pytest.raises(m1.M1Error) as e:
+        m1.m1_step_rk2(s.ctx, 1e-3)
+    assert e.value.status == m1.M1_ESTATE
+    s.close()
 
 
 @pytest.mark.parametrize("recon,riemann", [(1, 0), (2, 0), (0, 1)])
