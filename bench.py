@@ -272,7 +272,10 @@ def form_table(I):
             "c1_mg8_f32": (mg8, "f32", False), "c1_mg8_p64": (mg8, "p64", False),
             # the second-order step (two split steps and the average)
             "c3_f32_table_rk2": (I.make_c3, "f32", True), "c1_mg8_f32_rk2": (mg8, "f32", True),
-            "c1_f32_general": (general, "f32", False)}
+            "c1_f32_general": (general, "f32", False),
+            # the optically thin pulse the scheme's performance section times
+            # (256^3, scattering only, second-order steps)
+            "p0_pulse_f32_rk2": (I.make_pulse3d, "f32", True), "p0_pulse_p64_rk2": (I.make_pulse3d, "p64", True)}
 
 
 def main():

@@ -18,8 +18,9 @@ namespace m1 {
 //    root y, g = x y and h = y / 2 refined together, then two Newton
 //    corrections g <- g + (x - g^2) h; correctly rounded on every argument
 //    tried from 1e-300 to 1e300, with no range scaling or special-case
-//    handling beyond zero (the closure produces neither subnormal nor
-//    infinite arguments);
+//    handling beyond zero (the callers pass no subnormal or infinite
+//    arguments: squared norms below the smallest normal number are taken
+//    as zero before any reciprocal);
 //  * reciprocal square root: the hardware estimate refined by two Newton
 //    steps y <- y + y (1 - x y^2) / 2.
 // All stay far inside the 1e-12 parity tolerance.  FP32: the hardware
@@ -27,6 +28,9 @@ namespace m1 {
 // 1e-5.
 template <typename R> struct Num;
 template <> struct Num<double> {
+    // smallest normal number: |F|^2 below it is taken as F = 0, so that the
+    // inverse |F|^-2 stays finite
+    static constexpr double tiny = __DBL_MIN__;
     static __device__ __forceinline__ double sqrt_(double x)
     {
         const double y = __builtin_amdgcn_rsq(x);
@@ -56,6 +60,7 @@ template <> struct Num<double> {
     }
 };
 template <> struct Num<float> {
+    static constexpr float tiny = __FLT_MIN__;
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -81,7 +86,7 @@ __device__ __forceinline__ Wave<R> closure_wave(R E, R Fx, R Fy, R Fz)
 {
     Wave<R> w;
     const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    const R Fn = Num<R>::sqrt_(F2);
+    const R Fn = F2 >= Num<R>::tiny ? Num<R>::sqrt_(F2) : R(0);    // F = 0 below the normal range
     R f = Fn / E;
     f = f > R(1) ? R(1) : f;
     const R f2 = f * f;
@@ -196,7 +201,10 @@ __device__ __forceinline__ Wave<R> closure_wave_rt(R E, R Fx, R Fy, R Fz, int d)
     const R s = Num<R>::sqrt_(R(4) - R(3) * f2);
     // Levermore: xi = (3 + 4 f^2) / (5 + 2 s) = (5 - 2 s) / 3, so
     // (1 - xi) / 2 = (s - 1) / 3 and (3 xi - 1) / 2 = 2 - s
-    const R iFn = F2 > R(0) ? Num<R>::rsqrt(F2) : R(0);
+    // |F|^2 under the smallest normal number counts as F = 0: its inverse
+    // square would overflow, and a far-field flux that small (the numerical
+    // tail ahead of a front) carries no direction worth resolving
+    const R iFn = F2 >= Num<R>::tiny ? Num<R>::rsqrt(F2) : R(0);
     const R iF2 = iFn * iFn;
     const R Fd = d == 0 ? Fx : (d == 1 ? Fy : Fz);
     const R mu2 = Fd * Fd * iF2;
@@ -297,7 +305,8 @@ extern "C" __device__ float amdgcn_fmul_legacy(float, float) __asm("llvm.amdgcn.
 // van Leer limited slope without a branch, as
 // (dl |dr| + |dl| dr) / (|dl| + |dr|): the harmonic mean 2 dl dr / (dl + dr)
 // when the signs agree, zero when they differ or either is zero.  FP32 uses
-// the legacy multiply (0 x inf = 0), so dl = dr = 0 gives 0 without a select.
+// the legacy multiply (0 x inf = 0), so dl = dr = 0 gives 0 without a select
+// (and a subnormal |dl| + |dr|, whose reciprocal overflows, has num = 0).
 template <typename R>
 __device__ __forceinline__ R vanleer_fast(R dl, R dr);
 template <>
@@ -311,7 +320,9 @@ __device__ __forceinline__ double vanleer_fast<double>(double dl, double dr)
 {
     const double den = __builtin_fabs(dl) + __builtin_fabs(dr);
     const double num = __builtin_fma(__builtin_fabs(dl), dr, dl * __builtin_fabs(dr));
-    return den > 0.0 ? num * Num<double>::rcp(den) : 0.0;
+    // |dl| + |dr| under the smallest normal number gives 0 (the limited
+    // slope is below half of it), keeping the reciprocal finite
+    return den >= Num<double>::tiny ? num * Num<double>::rcp(den) : 0.0;
 }
 
 // HLL flux c_hat Phi* at the face between donor cells b (left) and c (right)
@@ -341,8 +352,9 @@ __device__ __forceinline__ void face_flux_s(int d, const R qb[4], const R qc[4],
     const Wave<R> wl = closure_wave_rt(UL[0], UL[1], UL[2], UL[3], d);
     const Wave<R> wr = closure_wave_rt(UR[0], UR[1], UR[2], UR[3], d);
     const R tau = R(0.5) * (tauL + tauR);
-    // optical-depth limit 4 / (3 tau) (none for tau = 0)
-    const R lim = tau > R(0) ? R(4) / R(3) * Num<R>::rcp(tau) : R(__builtin_inf());
+    // optical-depth limit 4 / (3 tau) (none for tau = 0, or below the
+    // normal range)
+    const R lim = tau >= Num<R>::tiny ? R(4) / R(3) * Num<R>::rcp(tau) : R(__builtin_inf());
     const R lamL = vmax(vmin(wl.lm, wr.lm), -lim);
     const R lamR = vmin(vmax(wl.lp, wr.lp), lim);
     if (riemann == M1_RIEMANN_LF) {

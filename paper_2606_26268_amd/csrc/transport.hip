@@ -93,11 +93,31 @@ __device__ __forceinline__ void load4(const TArgs<R> &a, int lin, R q[4])
     q[3] = a.U[3][lin];
 }
 
+// Whether the two faces of a cell along D carry the same area factor A / V:
+// every Cartesian direction, the azimuthal and axial directions of the
+// cylindrical grid and the azimuthal direction of the spherical grid.
+template <int GEOM, int D>
+constexpr bool same_area = GEOM == M1_CARTESIAN || (GEOM == M1_CYLINDRICAL && D > 0) ||
+                           (GEOM == M1_SPHERICAL && D == 2);
+
+// A_hi/V Phi_hi - A_lo/V Phi_lo of one direction.  With equal area factors
+// it is formed as a (Phi_hi - Phi_lo), so that equal face fluxes (a uniform
+// state) cancel exactly: the contracted a Phi_hi - a Phi_lo would leave the
+// rounding error of one product behind in every cell.
+template <bool SAME, typename R>
+__device__ __forceinline__ R face_diff(R al, R ah, R flo, R fhi)
+{
+    if constexpr (SAME)
+        return ah * (fhi - flo);
+    else
+        return ah * fhi - al * flo;
+}
+
 // Contribution of direction D to the flux divergence of the cell at index t
 // along D (row base `base`, stride `stride`): reconstruct cells t-1, t, t+1
 // (stencil t-2 .. t+2), take HLL fluxes at both faces of cell t and add
 // A_hi/V * Phi_hi - A_lo/V * Phi_lo to acc.
-template <typename R, int D>
+template <typename R, int D, int GEOM>
 __device__ __forceinline__ void direction_div(const TArgs<R> &a, int base, int stride, int t,
                                               R tr, R acc[4])
 {
@@ -142,7 +162,7 @@ __device__ __forceinline__ void direction_div(const TArgs<R> &a, int base, int s
     hll_flux<R, D>(Lt, Rp, R(0.5) * (t0 + tp), a.c_hat, fhi, a.riemann);
     const R al = a.m.alo[D][t] * tr, ah = a.m.ahi[D][t] * tr;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] += ah * fhi[v] - al * flo[v];
+    for (int v = 0; v < 4; ++v) acc[v] += face_diff<same_area<GEOM, D>>(al, ah, flo[v], fhi[v]);
 }
 
 template <typename R, int D>
@@ -171,7 +191,7 @@ __device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], Cen
         // |F|^2 and 1 / E
         const R f2 = vmin(cu.f2 * cu.ie * cu.ie, R(1));
         const R s = Num<R>::sqrt_(R(4) - R(3) * f2);
-        const R iF2 = cu.f2 > R(0) ? Num<R>::rcp(cu.f2) : R(0);
+        const R iF2 = cu.f2 >= Num<R>::tiny ? Num<R>::rcp(cu.f2) : R(0);
         const R iso = (s - R(1)) * (R(1) / R(3)) * U[0];
         const R an = (R(2) - s) * U[0] * iF2;
         const R k_ = a.dt * a.c_hat * ir;
@@ -218,16 +238,16 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
     load4(a, id, U);
     R acc[4] = {R(0), R(0), R(0), R(0)};
 
-    direction_div<R, 0>(a, id - i, 1, i, R(1), acc);
+    direction_div<R, 0, GEOM>(a, id - i, 1, i, R(1), acc);
     if (NDIM >= 2) {
         const R tr = a.m.trA[1][i];
-        direction_div<R, 1>(a, id - j * n0, n0, j, tr, acc);
+        direction_div<R, 1, GEOM>(a, id - j * n0, n0, j, tr, acc);
     } else if (a.ign[1]) {
         ignorable_div<R, 1>(a, U, a.m.trA[1][i], acc);
     }
     if (NDIM >= 3) {
         const R tr = a.m.trA[2][i] * a.m.trB[2][j];
-        direction_div<R, 2>(a, id - k * n0 * n1, n0 * n1, k, tr, acc);
+        direction_div<R, 2, GEOM>(a, id - k * n0 * n1, n0 * n1, k, tr, acc);
     } else if (a.ign[2]) {
         ignorable_div<R, 2>(a, U, a.m.trA[2][i] * a.m.trB[2][j], acc);
     }
@@ -525,8 +545,9 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1)
             const R azl = a.m.alo[2][k] * tr2, azh = a.m.ahi[2][k] * tr2;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                acc[v] = (axh * sfx[v][ly][lx + 1] - axl * sfx[v][ly][lx]) +
-                         (ayh * sfy[v][ly + 1][lx] - ayl * sfy[v][ly][lx]) + (azh * Fzhi[v] - azl * Fzlo[v]);
+                acc[v] = face_diff<same_area<GEOM, 0>>(axl, axh, sfx[v][ly][lx], sfx[v][ly][lx + 1]) +
+                         face_diff<same_area<GEOM, 1>>(ayl, ayh, sfy[v][ly][lx], sfy[v][ly + 1][lx]) +
+                         face_diff<same_area<GEOM, 2>>(azl, azh, Fzlo[v], Fzhi[v]);
             finish_cell<R, GEOM>(a, W[1], C1, acc, ir, ct, (k * n1 + j) * n0 + i);
         }
 #pragma unroll

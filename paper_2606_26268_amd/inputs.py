@@ -246,6 +246,32 @@ def make_c4(**kw):
     return p
 
 
+def make_pulse3d(N=256, dx=0.5, steps=100, cfl=0.4):
+    """The optically thin radiation pulse the scheme's performance section
+    times (the Sect. 3.4 pulse on a 3D Cartesian grid), in units a T0^4 = 1:
+    N^3 cells of width dx centred on the origin, periodic; radiation at
+    T_r = 1 + 100 exp(-r^2 / 25) (w = 5), i.e. E = T_r^4, F = 0; gas at rest
+    with rho = 1 and T = 1; no absorption (kappa = 0) and the constant
+    scattering of the paper's run, sigma rho = 3.9e4 cm^2/g x 1.67e-24 g/cm^3
+    x 1.496e13 cm = 9.74e-7 per unit length; c_hat = c = 1;
+    dt = cfl / (3 c_hat / dx)."""
+    half = 0.5 * N * dx
+    n = (N, N, N)
+    faces = [uniform_faces(N, -half, half) for _ in range(3)]
+    xc = 0.5 * (faces[0][1:] + faces[0][:-1])
+    r2 = xc[None, None, :] ** 2 + xc[None, :, None] ** 2 + xc[:, None, None] ** 2
+    gamma = 5.0 / 3.0
+    f = _zeros((N, N, N))
+    f["E"][:] = (1.0 + 100.0 * np.exp(-r2 / 25.0)) ** 4
+    f["rho"][:] = 1.0
+    f["Eg"][:] = 1.0 / (gamma - 1.0)
+    sigma = 3.9e4 * 1.67e-24 * 1.496e13
+    return Problem("p0", CARTESIAN, 3, n, faces, [[PERIODIC] * 2] * 3,
+                   c_hat=1.0, c=1.0, gamma=gamma,
+                   opacity=dict(kind=OPAC_CONSTANT, kP=0.0, kR=0.0, sigma=sigma),
+                   fields=f, dt=cfl / (3.0 / dx), steps=steps)
+
+
 # ----------------------------------------------------------------------------
 # MLP surrogate data (2 -> 64 -> 64 -> 2, tanh, linear 2 -> 2 shortcut)
 # ----------------------------------------------------------------------------

@@ -2,8 +2,9 @@
 benchmark times, for the forms that the other GPU tests check on reduced
 grids only: the network-opacity form on the spherical 192x96x192 grid, the
 eight-group box at 128^3 (split and second-order steps), the second-order
-step on the spherical grid with the table, and the general transport kernel (simple clip, Lax-Friedrichs
-flux, reflective walls, irradiation) on the 128^3 box."""
+step on the spherical grid with the table, the general transport kernel
+(simple clip, Lax-Friedrichs flux, reflective walls, irradiation) on the
+128^3 box, and the 256^3 radiation pulse with second-order steps."""
 import numpy as np
 import pytest
 
@@ -129,3 +130,44 @@ def test_general_kernel_full_size_steps(orc, precision):
         assert diag["counters"][:3] == list(cnt[:3])
     else:
         assert_close_f32(got, ref, label="general full f32")
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_pulse_full_size_rk2_steps(orc, precision):
+    """The pulse the scheme's performance section times, at 256^3 with
+    second-order steps (two of them), against the oracle; the FP64 result also
+    keeps the grid's mirror and axis-exchange symmetries.
+
+    The gas fields of this workload are ill-conditioned differences: the
+    scattering term dt c_hat sigma rho is 6.5e-8, so the momentum a step adds,
+    (F* - F') / c_hat, is 6.5e-8 of F / c_hat and carries the rounding of F
+    amplified by 1.5e7; and E reaches 1e8 against E_g = 1.5, so the energy
+    exchange writes the rounding of E into E_g.  The gas is judged against
+    the scales it inherits rounding from, F / c_hat and (c / c_hat) max E, as
+    the oracle's own response to a one-ulp change of E shows it must be."""
+    from paper_2606_26268_amd import m1
+    p = I.make_pulse3d()
+    say(f"case pulse 256^3 rk2 {precision}, 2 steps")
+    ref, _ = orc.Oracle(p).run(p.fields, p.dt, 2, rk2=True)
+    s = m1.Solver(p, precision, second_order=True)
+    s.step(p.dt, 2, rk2=True)
+    got = s.state()
+    s.close()
+    rad = ("E", "Fx", "Fy", "Fz")
+    tol = 1e-14 if precision == "p64" else 1e-6
+    if precision == "p64":
+        assert_close(got, ref, TOL_P64, fields=rad, label="pulse full p64")
+        E = got["E"]
+        assert np.abs(E - np.flip(E, 0)).max() <= 1e-12 * E.max()
+        assert np.abs(E - E.transpose(2, 1, 0)).max() <= 1e-12 * E.max()
+    else:
+        assert_close_f32(got, ref, fields=rad, label="pulse full f32")
+    for c in ("x", "y", "z"):
+        d = np.abs(got["m" + c] - ref["m" + c])
+        fs = np.abs(ref["F" + c]) / p.c_hat
+        say(f"  m{c}: sum|dm| / sum|F/c_hat| = {d.sum() / fs.sum():.1e}, max {d.max() / fs.max():.1e}")
+        assert d.sum() <= tol * fs.sum() and d.max() <= 10 * tol * fs.max(), c
+    d = np.abs(got["Eg"] - ref["Eg"])
+    es = (p.c / p.c_hat) * np.abs(ref["E"]).max()
+    say(f"  Eg: max|dEg| / (c/c_hat) max E = {d.max() / es:.1e}")
+    assert d.max() <= 10 * tol * es

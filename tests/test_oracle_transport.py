@@ -341,6 +341,35 @@ def test_spherical_pulse_decays_as_inverse_r_squared(orc):
     assert np.abs(a / a[-1] - 1).max() < 0.05, a
 
 
+def test_cartesian_3d_pulse_symmetry_and_conservation(orc):
+    """The Sect. 3.4 pulse on a 3D Cartesian grid, second-order steps, in the
+    recipe the performance workload uses (here 40^3 cells of width 0.5): the
+    total energy is conserved to rounding (no absorption, a periodic box), the
+    state keeps the grid's mirror and axis-exchange symmetries, the pulse
+    spreads, and the weak scattering hands momentum to the gas symmetrically."""
+    p = I.make_pulse3d(N=40, steps=12)
+    assert p.fields["E"].max() == pytest.approx((1 + 100 * math.exp(-3 * 0.25 ** 2 / 25)) ** 4)
+    assert p.fields["E"].min() == pytest.approx((1 + 100 * math.exp(-3 * 9.75 ** 2 / 25)) ** 4)
+    assert p.dt == pytest.approx(0.4 / 6.0)
+    out, cnt = orc.Oracle(p).run(p.fields, p.dt, p.steps, rk2=True)
+    E, Eg = out["E"], out["Eg"]
+    tot0 = (p.fields["E"] + p.fields["Eg"]).sum()
+    assert abs((E + Eg).sum() - tot0) <= 1e-13 * tot0
+    scale = E.max()
+    for ax in range(3):
+        assert np.abs(E - np.flip(E, ax)).max() <= 1e-12 * scale
+    assert np.abs(E - E.transpose(2, 1, 0)).max() <= 1e-12 * scale
+    assert np.abs(E - E.transpose(0, 2, 1)).max() <= 1e-12 * scale
+    # F points away from the centre: Fx odd in x, and Fx(x, y, z) = Fy(y, x, z)
+    assert np.abs(out["Fx"] + np.flip(out["Fx"], 2)).max() <= 1e-12 * scale
+    assert np.abs(out["Fx"] - out["Fy"].transpose(0, 2, 1)).max() <= 1e-12 * scale
+    assert out["Fx"][20, 20, 30] > 0 > out["Fx"][20, 20, 9]
+    assert E.max() < 0.95 * p.fields["E"].max()
+    # scattering transfers momentum: the gas moves with the radiation flux
+    assert (out["mx"][20, 20, 21:] > 0).all() and (out["mx"][20, 20, :19] < 0).all()
+    assert (cnt == 0).all()
+
+
 @pytest.mark.parametrize("vec", [(0.0, 0.0, 0.2), (0.1, 0.0, 0.0), (0.0, 0.1, 0.0)])
 def test_spherical_uniform_cartesian_flux_is_steady(orc, vec):
     """A uniform radiation field (E, F = const Cartesian vector) written in
