@@ -23,7 +23,9 @@ constexpr int NP = M1_MLP_NPARAM;
 constexpr int P_W1 = 0, P_B1 = 128, P_W2 = 192, P_B2 = 4288, P_W3 = 4352, P_B3 = 4480, P_WS = 4482;
 // transposed W2 fragments for back-propagation, after the inference pack
 constexpr int MLP_OFF_W2THI = MLP_PACK_FLOATS, MLP_OFF_W2TLO = MLP_PACK_FLOATS + 2048;
-constexpr int MLP_TRAIN_PACK = MLP_PACK_FLOATS + 4096;
+// then a copy of the flat parameters, from which the inference entries are derived
+constexpr int MLP_OFF_THETA = MLP_PACK_FLOATS + 4096;
+constexpr int MLP_TRAIN_PACK = MLP_OFF_THETA + NP;
 constexpr int LDS_STRIDE = 65;
 
 // ---------------------------------------------------------------------------
@@ -56,9 +58,24 @@ static inline float host_bf16_value(unsigned short b)
     return f;
 }
 
+// Inference entries of the packed network from the flat parameters: the
+// split fragments of A2 = s W2 (s = MLP_TANH_SCALE).  16 blocks of 256
+// threads, one W2 element each.
+__global__ void __launch_bounds__(256) k_mlp_pack_infer(const float *theta, float *pk)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int u = t >> 6, k = t & 63;
+    const float v = MLP_TANH_SCALE * theta[P_W2 + t];
+    const __bf16 h = to_bf16(v);
+    const __bf16 l = to_bf16(v - float(h));
+    reinterpret_cast<unsigned short *>(pk + MLP_OFF_A2HI)[frag_slot(u, k)] = __builtin_bit_cast(unsigned short, h);
+    reinterpret_cast<unsigned short *>(pk + MLP_OFF_A2LO)[frag_slot(u, k)] = __builtin_bit_cast(unsigned short, l);
+}
+
 static void host_pack(const float *th, const double *norm, std::vector<float> &pk)
 {
     pk.assign(MLP_TRAIN_PACK, 0.0f);
+    for (int i = 0; i < NP; ++i) pk[MLP_OFF_THETA + i] = th[i];
     for (int i = 0; i < 128; ++i) pk[MLP_OFF_W1 + i] = th[P_W1 + i];
     for (int i = 0; i < 64; ++i) pk[MLP_OFF_B1 + i] = th[P_B1 + i];
     for (int i = 0; i < 64; ++i) pk[MLP_OFF_B2 + i] = th[P_B2 + i];
@@ -93,6 +110,12 @@ int mlp_pack(m1_ctx *c, const float *theta, const double *norm)
         }
     }
     hipError_t e = hipMemcpy(c->mlp_dev, pk.data(), MLP_TRAIN_PACK * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mlp_pack_infer, dim3(16), dim3(256), 0, c->stream, c->mlp_dev + MLP_OFF_THETA,
+                           c->mlp_dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         set_error(std::string("MLP upload: ") + hipGetErrorString(e));
         return -3;
@@ -564,6 +587,11 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
         e = hipGetLastError();
     }
     hipEventRecord(ev1, c->stream);
+    if (e == hipSuccess) {
+        // the inference entries of the trained network
+        hipLaunchKernelGGL(k_mlp_pack_infer, dim3(16), dim3(256), 0, c->stream, theta, c->mlp_dev);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_mlp_eval, dim3((unsigned)n_eval_blocks), dim3(256), 0, c->stream, c->mlp_dev,
                            cfg->samples + 2 * cfg->n_train, cfg->n_eval, c->op, evmax);

@@ -33,10 +33,16 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 //   [390, 394)    norm: mean_P, std_P, mean_R, std_R
 //   [512, 2560)   W2 hi fragments: bf16 [mt 2][ks 4][lane 64][8]
 //   [2560, 4608)  W2 lo fragments, same order
-constexpr int MLP_PACK_FLOATS = 4608;
+//   [4608, 6656)  A2 hi fragments, A2 = s W2 (s = MLP_TANH_SCALE), same order
+//   [6656, 8704)  A2 lo fragments
+// (A2 serves the inference form below, whose second layer delivers the
+// scaled pre-activation s (W2 h1 + b2) = A2 h1 + s b2 directly)
+constexpr int MLP_PACK_FLOATS = 8704;
 constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 128, MLP_OFF_B2 = 192, MLP_OFF_W3 = 256;
 constexpr int MLP_OFF_B3 = 384, MLP_OFF_WS = 386, MLP_OFF_NORM = 390;
 constexpr int MLP_OFF_W2HI = 512, MLP_OFF_W2LO = 2560;
+constexpr int MLP_OFF_A2HI = 4608, MLP_OFF_A2LO = 6656;
+constexpr float MLP_TANH_SCALE = 2.8853900817779268f;   // 2 / ln 2
 
 __device__ __forceinline__ float fast_tanh(float x)
 {
@@ -202,11 +208,17 @@ struct MlpWave {
 // 16 ks + 8 g + e (ks = 2 mt + hs) that layer 2 wants from the lane as its
 // B operand: no hidden value changes lanes.
 //
-// tanh is evaluated as 1 - 2 / (1 + 2^z) with z = 2 log2(e) x; the factor
-// is folded into the staged first-layer weights and second-layer biases.
+// tanh is evaluated as 1 - 2 r with r = 1 / (1 + 2^z), z = 2 log2(e) x =
+// s x.  The factor s is folded into the staged first-layer weights and into
+// the second layer: its weights are A2 = s W2 (split hi + lo, packed with
+// the network) and its accumulator starts at s b2 (one more matrix product,
+// s b2 in three exact bfloat16 pieces against a column of ones), so the
+// matrix cores deliver z2 = s (W2 h1 + b2) directly; the output layer takes
+// h2 = 1 - 2 r2 as sum W3 - 2 sum W3 r2.  (Folding h1 = 1 - 2 r1 into the
+// second layer as well would save one more operation per unit, but the
+// products would then carry the split error of r1 ~ 1/2 where h1 is small:
+// six times the error against the exact network.)
 // ---------------------------------------------------------------------------
-
-constexpr float MLP_TANH_SCALE = 2.8853900817779268f;   // 2 / ln 2
 
 // tanh(z / MLP_TANH_SCALE); saturates to -1 and +1 for large |z|
 __device__ __forceinline__ float tanh_scaled(float z)
@@ -247,16 +259,17 @@ __host__ __device__ constexpr int mlp_l1_unit(int mt, int r)
 }
 
 struct MlpShared {
-    bf16x8 w2[2][2][4][64];   // [hi, lo][mt][ks][lane], 16 KiB
+    bf16x8 w2[2][2][4][64];   // A2 fragments [hi, lo][mt][ks][lane], 16 KiB
     bf16x8 w1[2][64];         // layer-1 A operand: [mt][lane]
-    float4 ep[2][2][16];      // [g][mt][i]: scaled b2, -2 W3[0], -2 W3[1] of the slot's unit
+    bf16x8 c2[2][64];         // s b2 as an A operand [mt][lane]: K slots 0..2 its three bfloat16 pieces
+    float2 ep[2][2][16];      // [g][mt][i]: -2 W3[0], -2 W3[1] of the slot's unit
     float w3sum[2];           // sum over units of W3[0], W3[1]
 };
 
 __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, int tid, int nthreads)
 {
-    const bf16x8 *hi = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_W2HI);
-    const bf16x8 *lo = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_W2LO);
+    const bf16x8 *hi = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_A2HI);
+    const bf16x8 *lo = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_A2LO);
     bf16x8 *dst = &sh.w2[0][0][0][0];
     for (int q = tid; q < 512; q += nthreads) {
         dst[q] = hi[q];
@@ -286,8 +299,20 @@ __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, in
     for (int q = tid; q < 64; q += nthreads) {
         const int g = q >> 5, mt = (q >> 4) & 1, i = q & 15;
         const int u = MlpWave::unit(mt, i, g);
-        sh.ep[g][mt][i] = make_float4(MLP_TANH_SCALE * packed[MLP_OFF_B2 + u], -2.0f * packed[MLP_OFF_W3 + u],
-                                      -2.0f * packed[MLP_OFF_W3 + 64 + u], 0.0f);
+        sh.ep[g][mt][i] = make_float2(-2.0f * packed[MLP_OFF_W3 + u], -2.0f * packed[MLP_OFF_W3 + 64 + u]);
+    }
+    // the accumulator's start s b2 enters through one more product, A = s b2
+    // in K slots 0..2 (exact three-piece split) against B = 1 in those slots
+    for (int q = tid; q < 128; q += nthreads) {
+        const int mt = q >> 6, l = q & 63;
+        unsigned hm, hl;
+        split3_bf16(MLP_TANH_SCALE * packed[MLP_OFF_B2 + 32 * mt + (l & 31)], hm, hl);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (l < 32) {
+            v.x = hm;              // K 0, 1: c2 hi, c2 mid
+            v.y = hl >> 16;        // K 2: c2 lo
+        }
+        sh.c2[mt][l] = __builtin_bit_cast(bf16x8, v);
     }
     if (tid < 64) {
         // fixed-order butterfly over the first wavefront: the same sums in
@@ -327,6 +352,9 @@ __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShar
         v.w = g ? 0x00003f80u : 0x3f803f80u;
         b1op[nt] = __builtin_bit_cast(bf16x8, v);
     }
+    // B operand of the bias product: 1 in K slots 0..2 (lanes of group 0)
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, g ? make_uint4(0u, 0u, 0u, 0u)
+                                                    : make_uint4(0x3f803f80u, 0x3f80u, 0u, 0u));
     f32x16 acc[2][2];
 #pragma unroll
     for (int m1 = 0; m1 < 2; ++m1) {
@@ -356,7 +384,9 @@ __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShar
                 const bf16x8 ah = sh.w2[0][mt][ks][lane], al = sh.w2[1][mt][ks][lane];
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt) {
-                    const f32x16 c0 = ks == 0 ? f32x16{} : acc[mt][nt];
+                    const f32x16 c0 = ks == 0 ? __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh.c2[mt][lane], ones,
+                                                                                         f32x16{}, 0, 0, 0)
+                                              : acc[mt][nt];
                     f32x16 t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nt], c0, 0, 0, 0);
                     t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nt], t, 0, 0, 0);
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nt], t, 0, 0, 0);
@@ -369,13 +399,12 @@ __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShar
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const float4 w = sh.ep[g][mt][i];
+            const float2 w = sh.ep[g][mt][i];
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
-                const float z = __builtin_fmaf(acc[mt][nt][i], MLP_TANH_SCALE, w.x);
-                const float r = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z));
-                part[nt][0] = __builtin_fmaf(w.y, r, part[nt][0]);
-                part[nt][1] = __builtin_fmaf(w.z, r, part[nt][1]);
+                const float r = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(acc[mt][nt][i]));
+                part[nt][0] = __builtin_fmaf(w.x, r, part[nt][0]);
+                part[nt][1] = __builtin_fmaf(w.y, r, part[nt][1]);
             }
         }
     // the partner lane holds the other 32 units of the same samples
