@@ -82,7 +82,10 @@ typedef struct {
  * a_rad   radiation constant a_R (default 1)
  * gamma   adiabatic index; C_v = rho / (gamma - 1) per volume (default 5/3)
  * precision  M1_P64 (all FP64) or M1_F32 (FP32 radiation storage and
- *         transport, FP64 implicit solve and gas)
+ *         transport, FP64 implicit solve and gas).  The closure works with
+ *         squared norms, so E and |F| should stay within about 1e-19..1e19
+ *         in M1_F32 (1e-154..1e154 in M1_P64); a flux whose squared norm is
+ *         below the normal range counts as zero
  * e_floor lower bound enforced on E after transport (default 1e-30)
  * recon   face treatment: M1_RECON_FPRESERVE (default, Eq. f_reconstruct),
  *         M1_RECON_PLUTO (flat face state whenever |R(F)| > R(E)) or
