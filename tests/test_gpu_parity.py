@@ -332,3 +332,29 @@ def test_flux_below_the_normal_range(orc, precision):
         full, _ = run_gpu(p, precision, 4, dt=dt)
         for k in ALL:
             assert np.isfinite(full[k]).all(), k
+
+
+THIN = [
+    (I.CARTESIAN, (40, 9, 1)), (I.CARTESIAN, (5, 3, 2)), (I.CARTESIAN, (1, 1, 1)), (I.CARTESIAN, (33, 1, 4)),
+    (I.CYLINDRICAL, (20, 3, 2)), (I.SPHERICAL, (24, 12, 2)),
+]
+
+
+@pytest.mark.parametrize("geom,n", THIN)
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_thin_and_tiny_3d_grids(orc, geom, n, precision):
+    """Three-dimensional grids with one, two or three cells along some
+    directions (periodic wraps that reach the same cell twice, outflow ghosts
+    that all copy one cell) and a single-cell grid, through the tiled
+    transport kernel, against the oracle."""
+    say(f"case thin 3D geom={geom} n={n} {precision}")
+    p = _problem(geom, n, 3, seed=300 + sum(n))
+    o = orc.Oracle(p)
+    dt = o.max_dt(0.4)
+    ref, cnt = o.run(p.fields, dt, 5)
+    got, diag = run_gpu(p, precision, 5, dt=dt)
+    if precision == "p64":
+        assert_close(got, ref, TOL_P64, label="thin p64")
+    else:
+        assert_close_f32(got, ref, label="thin f32")
+    assert diag["counters"][:3] == list(cnt[:3])
