@@ -24,7 +24,7 @@ def _run_gpu(p, precision, steps):
 
 
 @pytest.mark.parametrize("precision", ["p64", "f32"])
-@pytest.mark.parametrize("m", [2, 5])
+@pytest.mark.parametrize("m", [2, 5, 13, 32])
 def test_multigroup_box_parity(orc, precision, m):
     p = I.make_multigroup(m, (20, 20, 20), seed=3)
     p.c = 10 * p.c_hat
