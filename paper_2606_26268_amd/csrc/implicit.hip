@@ -65,15 +65,27 @@ __device__ __forceinline__ double gas_T_r(double inv_rho, double mx, double my, 
     return (Eg - 0.5 * (mx * mx + my * my + mz * mz) * inv_rho) * (gm1 * inv_rho);
 }
 
-// One cell of the implicit step; returns the new gas temperature.  Four
+// Element t of the run of cells starting at base: the block's base offset is
+// added to the array pointer on the scalar unit, so every access takes the
+// scalar base and one shared 32-bit lane offset (no per-array 64-bit address
+// arithmetic on the vector unit).
+template <typename P>
+__device__ __forceinline__ P &at(P *p, long base, unsigned t)
+{
+    return (p + base)[t];
+}
+
+// One cell of the implicit step (cell base + t of the block's run of cells);
+// returns the new gas temperature.  Four
 // FP64 reciprocals per cell (hardware estimate refined by two Newton steps,
 // about 1 ulp): 1/rho, the determinant, the flux damping factor and the
 // optical depth per length.
 template <typename R, bool CONST_OPAC>
-__device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, R hmax)
+__device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, unsigned t, R hmax)
 {
-    const double rho = a.rho[id];
-    double mx = a.gin[0][id], my = a.gin[1][id], mz = a.gin[2][id], Eg = a.gin[3][id];
+    const double rho = at(a.rho, base, t);
+    double mx = at(a.gin[0], base, t), my = at(a.gin[1], base, t), mz = at(a.gin[2], base, t);
+    double Eg = at(a.gin[3], base, t);
     const double inv_rho = Num<double>::rcp(rho);
     const double Cv = rho * a.k.inv_gm1;
     const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
@@ -82,11 +94,11 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, R hma
         rkP = rho * a.op.kP;
         rchi = rho * (a.op.kR + a.op.sigma);
     } else {
-        rkP = double(a.rkp[id]);
-        rchi = double(a.tau[id]) * Num<double>::rcp(double(hmax));
+        rkP = double(at(a.rkp, base, t));
+        rchi = double(at(a.tau, base, t)) * Num<double>::rcp(double(hmax));
     }
-    const double Es = double(a.Es[id]);
-    const double Fs[3] = {double(a.Fxs[id]), double(a.Fys[id]), double(a.Fzs[id])};
+    const double Es = double(at(a.Es, base, t));
+    const double Fs[3] = {double(at(a.Fxs, base, t)), double(at(a.Fys, base, t)), double(at(a.Fzs, base, t))};
     // Eq. implicit_matrix with gamma_abs,red = dt c_hat kappa_P rho and
     // gamma_abs = dt c kappa_P rho, inverted by Cramer's rule in a
     // cancellation-free arrangement (det > 0)
@@ -96,7 +108,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, R hma
     const double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
     // irradiation energy deposited in the step enters the S_1 row (Sect. 2.8)
     double S = 0.0;
-    if (a.irr) S = a.irr[id] * a.k.dt;
+    if (a.irr) S = at(a.irr, base, t) * a.k.dt;
     // uniform branch: the absorption-only form costs the default path nothing
     double E1;
     if (a.absorb)
@@ -123,21 +135,21 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, int id, R hma
     if (a.ravg[0]) {
         // second-order step: U^{n+1} = (U^n + U2) / 2 (the averaging partner
         // is read before this cell is written)
-        E1r = R(0.5 * (double(a.ravg[0][id]) + double(E1r)));
-        for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(a.ravg[1 + v][id]) + double(F1r[v])));
-        mx = 0.5 * (a.gavg[0][id] + mx);
-        my = 0.5 * (a.gavg[1][id] + my);
-        mz = 0.5 * (a.gavg[2][id] + mz);
-        Eg = 0.5 * (a.gavg[3][id] + Eg);
+        E1r = R(0.5 * (double(at(a.ravg[0], base, t)) + double(E1r)));
+        for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(at(a.ravg[1 + v], base, t)) + double(F1r[v])));
+        mx = 0.5 * (at(a.gavg[0], base, t) + mx);
+        my = 0.5 * (at(a.gavg[1], base, t) + my);
+        mz = 0.5 * (at(a.gavg[2], base, t) + mz);
+        Eg = 0.5 * (at(a.gavg[3], base, t) + Eg);
     }
-    a.E[id] = E1r;
-    a.Fx[id] = F1r[0];
-    a.Fy[id] = F1r[1];
-    a.Fz[id] = F1r[2];
-    a.Eg[id] = Eg;
-    a.mx[id] = mx;
-    a.my[id] = my;
-    a.mz[id] = mz;
+    at(a.E, base, t) = E1r;
+    at(a.Fx, base, t) = F1r[0];
+    at(a.Fy, base, t) = F1r[1];
+    at(a.Fz, base, t) = F1r[2];
+    at(a.Eg, base, t) = Eg;
+    at(a.mx, base, t) = mx;
+    at(a.my, base, t) = my;
+    at(a.mz, base, t) = mz;
     return gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
 }
 
@@ -146,19 +158,21 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
 {
     const int n0 = a.n[0], n1 = a.n[1];
     const int N = n0 * n1 * a.n[2];
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const long base = long(blockIdx.x) * blockDim.x;
+    const unsigned t = threadIdx.x;
+    const int id = int(base) + int(t);
     if (id >= N) return;
     int i, j, k;
     a.ix.split(id, i, j, k);
     // the cell extent serves both the optical depth read and the one written
     const R hm = OPK == OPK_CONST ? R(0) : cell_hmax(a.m, a.ndim, i, j, k);
-    const double T1 = implicit_cell<R, OPK == OPK_CONST>(a, id, hm);
+    const double T1 = implicit_cell<R, OPK == OPK_CONST>(a, base, t, hm);
     if (OPK != OPK_CONST) {
-        const R rho = R(a.rho[id]);
+        const R rho = R(at(a.rho, base, t));
         R kP, kR;
         opacity_analytic<R, OPK>(a.op, rho, R(T1), kP, kR);
-        a.rkp[id] = rho * kP;
-        a.tau[id] = rho * (kR + R(a.op.sigma)) * hm;
+        at(a.rkp, base, t) = rho * kP;
+        at(a.tau, base, t) = rho * (kR + R(a.op.sigma)) * hm;
     }
 }
 
@@ -176,22 +190,24 @@ __global__ void __launch_bounds__(256, 4) k_implicit_mlp(IArgs<R> a)
     const int lane = threadIdx.x & 63;
     __shared__ MlpShared sh;
     {
-        const int id = blockIdx.x * blockDim.x + threadIdx.x;
+        const long base = long(blockIdx.x) * blockDim.x;
+        const unsigned t = threadIdx.x;
+        const int id = int(base) + int(t);
         const bool live = id < N;
         const int idc = live ? id : N - 1;
         int i, j, k;
         a.ix.split(idc, i, j, k);
         const R hm = cell_hmax(a.m, a.ndim, i, j, k);
         double T1 = 1.0;
-        if (live) T1 = implicit_cell<R, false>(a, id, hm);
+        if (live) T1 = implicit_cell<R, false>(a, base, t, hm);
         const float rho = float(a.rho[idc]);
         mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
         __syncthreads();
         float kP, kR;
         mlp_opacity_shared(a.op, sh, rho, float(T1), lane, kP, kR);
         if (live) {
-            a.rkp[id] = R(rho * kP);
-            a.tau[id] = R(rho * (kR + float(a.op.sigma))) * hm;
+            at(a.rkp, base, t) = R(rho * kP);
+            at(a.tau, base, t) = R(rho * (kR + float(a.op.sigma))) * hm;
         }
     }
 }
