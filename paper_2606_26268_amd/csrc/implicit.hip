@@ -324,42 +324,42 @@ static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met, int stage
 // ---------------------------------------------------------------------------
 
 // Fraction of the Planck energy density below x = h nu / k T,
-// (15 / pi^4) int_0^x t^3 / (e^t - 1) dt.  Below x = 1: the power series of
-// t^3 / (e^t - 1) integrated term by term (coefficients B_k / ((k + 3) k!),
-// B_k the Bernoulli numbers); above: 1 minus the tail
-// sum_n e^{-n x} (x^3/n + 3 x^2/n^2 + 6 x/n^3 + 6/n^4), summed until the
-// terms drop below double precision.
-// 1/n for the Planck tail: exact reciprocals of the first integers from a
-// table, a division beyond it
-__device__ __forceinline__ double inv_int(int n, double dn)
-{
-    constexpr double T[17] = {0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9,
-                              1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16};
-    return n <= 16 ? T[n] : 1.0 / dn;
-}
-
+// (15 / pi^4) int_0^x t^3 / (e^t - 1) dt.  Below x = 5/2: the power series
+// of t^3 / (e^t - 1) integrated term by term, coefficients B_k / ((k + 3) k!)
+// with B_k the Bernoulli numbers, through k = 42 (the series converges for
+// x < 2 pi; at x = 5/2 the omitted terms are below 2e-18 of the sum); above:
+// 1 minus the tail sum_n e^{-n x} (x^3/n + 3 x^2/n^2 + 6 x/n^3 + 6/n^4),
+// summed until its terms drop below double precision (at most 17 of them
+// above 5/2).  The split at 5/2 rather than 1 bounds the tail loop, whose
+// length otherwise grows as 1/x and dominated the multigroup implicit step.
 __device__ double planck_fraction(double x)
 {
     constexpr double NORM = 0.15398973382026503;   // 15 / pi^4
     if (x <= 0.0) return 0.0;
-    if (x < 1.0) {
-        // B_k / ((k + 3) k!) for k = 0, 1, 2, 4, 6, ..., 18 (odd B_k > 1 vanish)
-        constexpr double C[11] = {
-            1.0 / 3.0, -1.0 / 8.0, 1.0 / 60.0, -1.0 / 5040.0, 1.0 / 272160.0, -1.0 / 13305600.0,
-            1.0 / 622702080.0, -691.0 / 19615115520000.0, 1.0 / 1270312243200.0,
-            -3617.0 / 202741834014720000.0, 43867.0 / 107290978560589824000.0};
+    if (x < 2.5) {
+        // B_k / ((k + 3) k!) for k = 2, 4, ..., 42 (odd B_k > 1 vanish)
+        constexpr double C[21] = {
+            0.016666666666666666, -0.00019841269841269841, 3.6743092298647855e-06, -7.5156325156325161e-08,
+            1.6059043836821615e-09, -3.5227934257916621e-11, 7.8720803121674577e-13, -1.7840422612224122e-14,
+            4.0886009791799258e-16, -9.4559508632959214e-18, 2.2036011313440918e-19, -5.1683202540046385e-21,
+            1.2188644964239542e-22, -2.8882314280766281e-24, 6.8725831889020704e-26, -1.641368762534915e-27,
+            3.9328985827428784e-29, -9.451269078629001e-31, 2.2772522578280597e-32, -5.5000521295363484e-34,
+            1.3312603916626966e-35};
         const double x2 = x * x;
-        // x^3 (C0 + C1 x + x^2 (C2 + C3 x^2 + C4 x^4 + ...))
-        double p = C[10];
-        for (int j = 9; j >= 2; --j) p = p * x2 + C[j];
-        const double series = C[0] + x * C[1] + x2 * p;
+        // x^3 (1/3 - x/8 + x^2 (C_2 + C_4 x^2 + ...))
+        double p = C[20];
+        for (int j = 19; j >= 0; --j) p = __builtin_fma(p, x2, C[j]);
+        const double series = (1.0 / 3.0) + x * (-0.125) + x2 * p;
         return NORM * x * x2 * series;
     }
+    // 1/n, n = 1 .. 17 (the most terms the tail takes above 5/2)
+    constexpr double RN[18] = {0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9,
+                               1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17};
     const double e1 = exp(-x);
     const double x2 = x * x, x3 = x2 * x;
-    double e = e1, tail = 0.0, dn = 1.0;
-    for (int n = 1; n <= 48 && e > 1e-18 * e1; ++n, dn += 1.0) {
-        const double rn = inv_int(n, dn);
+    double e = e1, tail = 0.0;
+    for (int n = 1; n <= 17 && e > 1e-18 * e1; ++n) {
+        const double rn = RN[n];
         tail += e * rn * (x3 + rn * (3.0 * x2 + rn * (6.0 * x + rn * 6.0)));
         e *= e1;
     }
@@ -405,12 +405,12 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
     const int m = g.gp.m;
     const double rho = a.rho[id];
     double mx = a.gin[0][id], my = a.gin[1][id], mz = a.gin[2][id], Eg = a.gin[3][id];
-    const double inv_rho = 1.0 / rho;
+    const double inv_rho = Num<double>::rcp(rho);
     const double Cv = rho * a.k.inv_gm1;
     const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
     const double S = a.irr ? a.irr[id] * a.k.dt : 0.0;
     const double aT3 = a.k.a * T * T * T;
-    const double iT = 1.0 / T;
+    const double iT = Num<double>::rcp(T);
     // pass 1: group fractions, transported energies and the reduced equation
     // for the temperature (per-group values stay in registers: MG >= m)
     double b[MG], Es[MG], inv1[MG];
@@ -423,13 +423,13 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
             lo = hi;
             Es[q] = double(reinterpret_cast<const R *>(g.star + 4 * q * g.plane)[id]);
             const double kr = rho * g.gp.kP[q];
-            inv1[q] = 1.0 / (1.0 + a.k.dt_ch * kr);
+            inv1[q] = Num<double>::rcp(1.0 + a.k.dt_ch * kr);
             const double gg = a.k.dt_c * kr;
             D += 4.0 * gg * b[q] * aT3 * inv1[q];
             Lnum += 4.0 * gg * Es[q] * inv1[q];
         }
     }
-    const double L = aT3 * Lnum / D;
+    const double L = aT3 * Lnum * Num<double>::rcp(D);
     // pass 2: group energies, damped fluxes, rescaled totals
     double dE = 0.0, dF[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
         if (q < m) {
             const double gr = a.k.dt_ch * rho * g.gp.kP[q];
             const double E1 = a.absorb ? Es[q] * inv1[q] : (Es[q] + gr * b[q] * L) * inv1[q];
-            const double inv_damp = 1.0 / (1.0 + a.k.dt_ch * rho * (g.gp.kR[q] + g.gp.sigma));
+            const double inv_damp = Num<double>::rcp(1.0 + a.k.dt_ch * rho * (g.gp.kR[q] + g.gp.sigma));
             double F1[3], Fs[3];
             for (int v = 0; v < 3; ++v) {
                 Fs[v] = double(reinterpret_cast<const R *>(g.star + (4 * q + 1 + v) * g.plane)[id]);
