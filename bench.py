@@ -68,7 +68,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    # the GPU clock ramps up over the first 100-150 steps of sustained
+    # stepping (ms/step falls by 10-30 %); the default warm-up covers it
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--only", action="store_true", help="time the headline form only")
     ap.add_argument("--form", default=None, help="time one named form alone and print its figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
