@@ -118,13 +118,14 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, un
     const double inv_damp = Num<double>::rcp(1.0 + a.k.dt_ch * rchi);   // Eq. source_discrete2
     double F1[3] = {Fs[0] * inv_damp, Fs[1] * inv_damp, Fs[2] * inv_damp};
     const double Fn = Num<double>::sqrt_(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
-    if (Fn > E1) {
+    const bool clipped = Fn > E1;
+    if (clipped) {
         const double s = E1 / Fn;
         F1[0] *= s;
         F1[1] *= s;
         F1[2] *= s;
-        atomicAdd(&a.cnt[2], 1ull);
     }
+    count_hits(a.cnt, 2, clipped);
     // stored (possibly float) values define the exchanged amounts, so the
     // rescaled totals E_g + (c/c_hat) E and m + F/c_hat are conserved
     R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
@@ -444,13 +445,14 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
                 F1[v] = Fs[v] * inv_damp;
             }
             const double Fn = Num<double>::sqrt_(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
-            if (Fn > E1) {
+            const bool clipped = Fn > E1;
+            if (clipped) {
                 const double sc = E1 / Fn;
                 F1[0] *= sc;
                 F1[1] *= sc;
                 F1[2] *= sc;
-                atomicAdd(&a.cnt[2], 1ull);
             }
+            count_hits(a.cnt, 2, clipped);
             R E1r = R(E1), F1r[3] = {R(F1[0]), R(F1[1]), R(F1[2])};
             dE += double(E1r) - Es[q];
             for (int v = 0; v < 3; ++v) dF[v] += double(F1r[v]) - Fs[v];

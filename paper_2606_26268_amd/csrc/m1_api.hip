@@ -350,7 +350,7 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     // transported state and optical depth per group, the rho kappa_P cache
     const int G = c->grp.m;
     const size_t nfield = 5 * (size_t)G + 1;
-    const size_t bytes = nfield * per + 256 + ndiag * sizeof(double);
+    const size_t bytes = nfield * per + CNT_BYTES + ndiag * sizeof(double);
     if (c->scratch) {
         hipFree(c->scratch);
         c->scratch = nullptr;
@@ -380,8 +380,8 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     c->tau = b + 4 * (size_t)G * per;
     c->rkp = b + 5 * (size_t)G * per;
     c->cnt = reinterpret_cast<unsigned long long *>(b + nfield * per);
-    c->partials = reinterpret_cast<double *>(b + nfield * per + 256);
-    e = hipMemsetAsync(c->cnt, 0, 4 * sizeof(unsigned long long), c->stream);
+    c->partials = reinterpret_cast<double *>(b + nfield * per + CNT_BYTES);
+    e = hipMemsetAsync(c->cnt, 0, CNT_BYTES, c->stream);
     if (e != hipSuccess) return hip_fail(e, "m1_bind_state: counter reset");
     c->f = *f;
     c->bound = true;
@@ -674,9 +674,12 @@ m1_status m1_diagnostics(m1_ctx *c, m1_diag *out)
     double v[8];
     hipError_t e = launch_diag(c, v);
     if (e != hipSuccess) return hip_fail(e, "m1_diagnostics");
-    unsigned long long cnt[4];
-    e = hipMemcpy(cnt, c->cnt, sizeof(cnt), hipMemcpyDeviceToHost);
+    std::vector<unsigned long long> slots(CNT_BYTES / sizeof(unsigned long long));
+    e = hipMemcpy(slots.data(), c->cnt, CNT_BYTES, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "m1_diagnostics counters");
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i)
+        for (int s = 0; s < CNT_SLOTS; ++s) cnt[i] += slots[(size_t(i) * CNT_SLOTS + s) * CNT_STRIDE];
     out->rad_energy = v[0];
     out->total_energy = v[1];
     out->momentum[0] = v[2];

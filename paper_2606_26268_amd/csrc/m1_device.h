@@ -66,6 +66,22 @@ template <> struct Num<float> {
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 };
 
+// Adds to counter `which` the number of active lanes of the wavefront with
+// hit set, by one atomic from the lowest such lane into the wavefront's slot
+// of the counter (every active lane calls it).  Fix-up counters see up to
+// millions of events per launch (a multigroup step clips several per cent of
+// its cell-groups); atomics of every wavefront on one address serialised
+// them and more than doubled the multigroup implicit step.
+__device__ __forceinline__ void count_hits(unsigned long long *cnt, int which, bool hit)
+{
+    const unsigned long long m = __ballot(hit);
+    if (m != 0ull && __lane_id() == unsigned(__ffsll((long long)m) - 1)) {
+        const unsigned wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        const unsigned slot = wave & (CNT_SLOTS - 1);
+        atomicAdd(cnt + (size_t(which) * CNT_SLOTS + slot) * CNT_STRIDE, (unsigned long long)__popcll(m));
+    }
+}
+
 // minimum / maximum as single instructions (finite arguments)
 __device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }

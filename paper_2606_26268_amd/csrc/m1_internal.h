@@ -100,6 +100,13 @@ struct ImplicitConsts {
 
 } // namespace m1
 
+// Fix-up counters: each of the 4 is spread over CNT_SLOTS slots, one per
+// 128-byte line (slot s of counter c at cnt[(c * CNT_SLOTS + s) * CNT_STRIDE]);
+// a wavefront adds to the slot of its index, the host sums the slots.  A
+// single address per counter serialised the atomics of every wavefront.
+constexpr int CNT_SLOTS = 64, CNT_STRIDE = 16;
+constexpr size_t CNT_BYTES = size_t(4) * CNT_SLOTS * CNT_STRIDE * sizeof(unsigned long long);
+
 struct m1_ctx {
     int ndim = 1;
     int n[3] = {1, 1, 1};
@@ -129,7 +136,7 @@ struct m1_ctx {
     void *scratch = nullptr;  // E*, Fx*, Fy*, Fz*, tau, rkp (form precision)
     void *star[4] = {nullptr, nullptr, nullptr, nullptr};
     void *tau = nullptr, *rkp = nullptr;
-    unsigned long long *cnt = nullptr;     // 4 fix-up counters
+    unsigned long long *cnt = nullptr;     // 4 fix-up counters, CNT_SLOTS slots each
     double *partials = nullptr;            // reduction scratch
     int npartial = 0;
     bool transported = false;

@@ -209,18 +209,18 @@ __device__ __forceinline__ void finish_cell(const TArgs<R> &a, const R U[4], Cen
     }
 
     // positivity floor on E, then f <= 1 at the cell centre
-    if (Us[0] < a.e_floor) {
-        Us[0] = a.e_floor;
-        atomicAdd(&a.cnt[0], 1ull);
-    }
+    const bool floored = Us[0] < a.e_floor;
+    if (floored) Us[0] = a.e_floor;
+    count_hits(a.cnt, 0, floored);
     const R Fn = Num<R>::sqrt_(Us[1] * Us[1] + Us[2] * Us[2] + Us[3] * Us[3]);
-    if (Fn > Us[0]) {
+    const bool clipped = Fn > Us[0];
+    if (clipped) {
         const R sc = Us[0] * Num<R>::rcp(Fn);
         Us[1] *= sc;
         Us[2] *= sc;
         Us[3] *= sc;
-        atomicAdd(&a.cnt[1], 1ull);
     }
+    count_hits(a.cnt, 1, clipped);
 #pragma unroll
     for (int v = 0; v < 4; ++v) a.out[v][id] = Us[v];
 }
