@@ -290,10 +290,9 @@ __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
     return tid - (nx - NT) < ny - NT ? NT + tid - (nx - NT) : -1;
 }
 
-// FP32 instantiations ask for at least four (default) and three (general)
-// waves per SIMD -- with 256-thread blocks, as many resident blocks per CU --
-// i.e. at most 128 and 168 VGPRs: the general one just exceeds its bound
-// otherwise, the default one fits exactly.
+// FP32 instantiations are held to four (default) and three (general)
+// resident blocks per CU, at most 128 and 168 VGPRs: the general one just
+// exceeds its bound otherwise, the default one fits exactly.
 template <typename R, int GEOM, bool GENERAL>
 __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1)
     k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
