@@ -358,3 +358,33 @@ def test_thin_and_tiny_3d_grids(orc, geom, n, precision):
     else:
         assert_close_f32(got, ref, label="thin f32")
     assert diag["counters"][:3] == list(cnt[:3])
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_pulse_long_run(orc, precision):
+    """The pulse recipe on 64^3 cells for 40 second-order steps: the front
+    crosses the box's outer cells, where the flux grows from exactly zero
+    through values whose squares leave the normal range (the regime in which
+    the FP32 closure once returned NaN).  Radiation against the oracle; the
+    gas is judged against the scales it inherits rounding from, as in the
+    full-size pulse test."""
+    p = I.make_pulse3d(N=64, steps=40)
+    say(f"case pulse 64^3 rk2 {precision}, 40 steps")
+    ref, _ = orc.Oracle(p).run(p.fields, p.dt, p.steps, rk2=True)
+    from paper_2606_26268_amd import m1
+    s = m1.Solver(p, precision, second_order=True)
+    s.step(p.dt, p.steps, rk2=True)
+    got = s.state()
+    s.close()
+    for k in ALL:
+        assert np.isfinite(got[k]).all(), k
+    if precision == "p64":
+        assert_close(got, ref, TOL_P64, fields=RAD, label="pulse 64 p64")
+    else:
+        assert_close_f32(got, ref, fields=RAD, label="pulse 64 f32")
+    tol = 1e-14 if precision == "p64" else 1e-6
+    for c in ("x", "y", "z"):
+        d = np.abs(got["m" + c] - ref["m" + c])
+        assert d.sum() <= tol * (np.abs(ref["F" + c]).sum() / p.c_hat), c
+    es = (p.c / p.c_hat) * np.abs(ref["E"]).max()
+    assert np.abs(got["Eg"] - ref["Eg"]).max() <= 10 * tol * es
