@@ -257,7 +257,8 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
 }
 
 // ---------------------------------------------------------------------------
-// 3D tiled kernel: a block owns a TX x TY column of cells and marches along z
+// 3D tiled kernel: a block owns a TX x TY column of cells (Tile below) and
+// marches along z
 // over a chunk of planes.  Per plane: (1) the state with a two-cell halo in
 // x and y (cross-shaped, no corners) is staged in LDS; (2) van Leer slopes
 // of every cell that donates to a face of the tile are computed once per
@@ -269,18 +270,33 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
 // Each thread's slope and face assignments are the same in every plane, so
 // their metric factors are loaded once, before the march.
 // ---------------------------------------------------------------------------
-constexpr int TX = 32, TY = 8, HX = TX + 4, HY = TY + 4, NT = TX * TY;
-constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX, NHALO = 2 * (2 * TY + 2 * TX);
-constexpr int NXS = TY * (TX + 2), NYS = (TY + 2) * TX;
-// Task passes of the slope and face stages: pass 0 takes x tasks 0 .. NT-1,
-// pass 1 y tasks 0 .. NT-1, pass 2 the rest of both (x first), so that the
-// first two passes run with their direction fixed at compile time.
-static_assert(NXF >= NT && NYF >= NT && NXS >= NT && NYS >= NT, "tile too small for the task passes");
-static_assert(NXF + NYF <= 3 * NT && NXS + NYS <= 3 * NT, "tile too large for three task passes");
+// Tile of a block: TX x TY cells, one thread per cell.  32 x 16 (512
+// threads) for every kernel but the general FP32 one, which keeps 32 x 8: its
+// 150 VGPRs allow three waves per SIMD only in 256-thread blocks.  The taller
+// tile computes 4 % fewer halo faces and slopes per cell (default kernels
+// 1.5 % faster in FP32, 3 % in FP64); FP32 blocks take 55 KB of LDS (two per
+// CU, four waves per SIMD), FP64 blocks 110 KB (one per CU, the two waves
+// per SIMD their registers allow anyway).
+template <int TY_>
+struct Tile {
+    static constexpr int TX = 32, TY = TY_, HX = TX + 4, HY = TY + 4, NT = TX * TY;
+    static constexpr int NXF = TY * (TX + 1), NYF = (TY + 1) * TX, NHALO = 2 * (2 * TY + 2 * TX);
+    static constexpr int NXS = TY * (TX + 2), NYS = (TY + 2) * TX;
+    // Task passes of the slope and face stages: pass 0 takes x tasks
+    // 0 .. NT-1, pass 1 y tasks 0 .. NT-1, pass 2 the rest of both (x first),
+    // so that the first two passes run with their direction fixed at compile
+    // time.
+    static_assert(NXF >= NT && NYF >= NT && NXS >= NT && NYS >= NT, "tile too small for the task passes");
+    static_assert(NXF + NYF <= 3 * NT && NXS + NYS <= 3 * NT, "tile too large for three task passes");
+    static_assert(NHALO <= NT, "one halo cell per thread at most");
+};
+template <typename R, bool GENERAL>
+using TileOf = Tile<(sizeof(R) == 4 && GENERAL) ? 8 : 16>;
 constexpr int NSP = 3, NFP = 3;
 
 // task of thread tid in pass p: direction (0 = x, 1 = y) and index within
 // that direction's tasks, or -1 past the last (nx, ny: task counts)
+template <int NT>
 __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
 {
     dir = p == 1 ? 1 : 0;
@@ -290,13 +306,17 @@ __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
     return tid - (nx - NT) < ny - NT ? NT + tid - (nx - NT) : -1;
 }
 
-// FP32 instantiations are held to four (default) and three (general)
-// resident blocks per CU, at most 128 and 168 VGPRs: the general one just
-// exceeds its bound otherwise, the default one fits exactly.
+// FP32 instantiations ask for at least four (default) and three (general)
+// waves per SIMD (the second argument of the bound), i.e. at most 128 and
+// 168 VGPRs: the general one just exceeds its bound otherwise, the default
+// one fits exactly.
 template <typename R, int GEOM, bool GENERAL>
-__global__ void __launch_bounds__(NT, sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1)
+__global__ void __launch_bounds__((TileOf<R, GENERAL>::NT), (sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1))
     k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
 {
+    using T = TileOf<R, GENERAL>;
+    constexpr int TX = T::TX, TY = T::TY, HX = T::HX, HY = T::HY, NT = T::NT;
+    constexpr int NXF = T::NXF, NYF = T::NYF, NHALO = T::NHALO, NXS = T::NXS, NYS = T::NYS;
     select_group(a);
     // the default scheme (f-preserving fix + HLL, periodic / outflow sides)
     // is compiled without the variant and ghost-state code
@@ -362,7 +382,7 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1)
 #pragma unroll
     for (int p = 0; p < NSP; ++p) {
         int dir;
-        const int q = task_of(p, tid, NXS, NYS, dir);
+        const int q = task_of<NT>(p, tid, NXS, NYS, dir);
         s_on[p] = false;
         s_ctr[p] = 2 * HX + 2;
         s_str[p] = 1;
@@ -395,7 +415,7 @@ __global__ void __launch_bounds__(NT, sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1)
 #pragma unroll
     for (int p = 0; p < NFP; ++p) {
         int dir;
-        const int q = task_of(p, tid, NXF, NYF, dir);
+        const int q = task_of<NT>(p, tid, NXF, NYF, dir);
         f_on[p] = false;
         f_d[p] = 0;
         f_b[p] = f_sb[p] = f_o[p] = 0;
@@ -594,6 +614,8 @@ static int resident_blocks(const void *kern, int block)
 template <typename R, int GEOM, bool GENERAL>
 static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
 {
+    using T = TileOf<R, GENERAL>;
+    constexpr int TX = T::TX, TY = T::TY, NT = T::NT;
     const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
     const long slots = resident_blocks(reinterpret_cast<const void *>(&k_transport3d<R, GEOM, GENERAL>), NT);
     int nz = 8;
