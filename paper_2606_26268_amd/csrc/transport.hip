@@ -270,13 +270,13 @@ __global__ void __launch_bounds__(256) k_transport(TArgs<R> a)
 // Each thread's slope and face assignments are the same in every plane, so
 // their metric factors are loaded once, before the march.
 // ---------------------------------------------------------------------------
-// Tile of a block: TX x TY cells, one thread per cell.  32 x 16 (512
-// threads) for every kernel but the general FP32 one, which keeps 32 x 8: its
-// 150 VGPRs allow three waves per SIMD only in 256-thread blocks.  The taller
-// tile computes 4 % fewer halo faces and slopes per cell (default kernels
-// 1.5 % faster in FP32, 3 % in FP64); FP32 blocks take 55 KB of LDS (two per
-// CU, four waves per SIMD), FP64 blocks 110 KB (one per CU, the two waves
-// per SIMD their registers allow anyway).
+// Tile of a block: TX x TY cells, one thread per cell, TY = 8 (256 threads)
+// or 16 (512 threads).  The taller tile computes 4 % fewer halo faces and
+// slopes per cell; FP32 blocks of it take 55 KB of LDS (two per CU, four
+// waves per SIMD), FP64 blocks 110 KB (one per CU, the two waves per SIMD
+// their registers allow anyway).  The general FP32 kernel has only the
+// 32 x 8 tile: its 150 VGPRs allow three waves per SIMD only in 256-thread
+// blocks.
 template <int TY_>
 struct Tile {
     static constexpr int TX = 32, TY = TY_, HX = TX + 4, HY = TY + 4, NT = TX * TY;
@@ -290,8 +290,6 @@ struct Tile {
     static_assert(NXF + NYF <= 3 * NT && NXS + NYS <= 3 * NT, "tile too large for three task passes");
     static_assert(NHALO <= NT, "one halo cell per thread at most");
 };
-template <typename R, bool GENERAL>
-using TileOf = Tile<(sizeof(R) == 4 && GENERAL) ? 8 : 16>;
 constexpr int NSP = 3, NFP = 3;
 
 // task of thread tid in pass p: direction (0 = x, 1 = y) and index within
@@ -310,11 +308,11 @@ __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
 // waves per SIMD (the second argument of the bound), i.e. at most 128 and
 // 168 VGPRs: the general one just exceeds its bound otherwise, the default
 // one fits exactly.
-template <typename R, int GEOM, bool GENERAL>
-__global__ void __launch_bounds__((TileOf<R, GENERAL>::NT), (sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1))
+template <typename R, int GEOM, bool GENERAL, int TYB>
+__global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1))
     k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
 {
-    using T = TileOf<R, GENERAL>;
+    using T = Tile<TYB>;
     constexpr int TX = T::TX, TY = T::TY, HX = T::HX, HY = T::HY, NT = T::NT;
     constexpr int NXF = T::NXF, NYF = T::NYF, NHALO = T::NHALO, NXS = T::NXS, NYS = T::NYS;
     select_group(a);
@@ -611,27 +609,48 @@ static int resident_blocks(const void *kern, int block)
 // planes), the 28-64-plane chunks this cost picks without the cap were 4-6 %
 // slower than 16 (fewer blocks to balance, more halo misses in L2); with the
 // cap it lands on the fastest chunk measured or within 3 % of it.
-template <typename R, int GEOM, bool GENERAL>
-static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
+// Launch with tile height TYB; with single_round, only if the launch then
+// fits in one round of resident blocks (returns whether it launched).
+template <typename R, int GEOM, bool GENERAL, int TYB>
+static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, bool single_round)
 {
-    using T = TileOf<R, GENERAL>;
+    using T = Tile<TYB>;
     constexpr int TX = T::TX, TY = T::TY, NT = T::NT;
     const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
-    const long slots = resident_blocks(reinterpret_cast<const void *>(&k_transport3d<R, GEOM, GENERAL>), NT);
+    const long slots = resident_blocks(reinterpret_cast<const void *>(&k_transport3d<R, GEOM, GENERAL, TYB>), NT);
     int nz = 8;
     double best = 1e300;
+    long rounds = 1;
     for (int z = 2; z <= 16; ++z) {
         const long nb = long(tiles_x) * tiles_y * ((c->n[2] + z - 1) / z) * ngrp;
-        const double cost = double((nb + slots - 1) / slots) * (z + 1);
+        const long r = (nb + slots - 1) / slots;
+        const double cost = double(r) * (z + 1);
         if (cost < best) {
             best = cost;
             nz = z;
+            rounds = r;
         }
     }
+    if (single_round && rounds > 1) return false;
     const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
     const int launched = ((nblocks + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_transport3d<R, GEOM, GENERAL>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz,
+    hipLaunchKernelGGL((k_transport3d<R, GEOM, GENERAL, TYB>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz,
                        tiles_x, tiles_y, nblocks);
+    return true;
+}
+
+// The 32 x 16 tile where its launch fits in one round of resident blocks
+// (the 192x96x192 and 128^3 grids: 1.5-3 % faster transport than 32 x 8),
+// else 32 x 8 (on the 256^3 grid and eight groups at 128^3, launches of
+// several rounds, the taller blocks were 2-4 % slower: they leave a compute
+// unit half idle whenever one of its two blocks finishes).
+template <typename R, int GEOM, bool GENERAL>
+static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
+{
+    if constexpr (!(sizeof(R) == 4 && GENERAL)) {
+        if (launch_tile<R, GEOM, GENERAL, 16>(c, a, ngrp, true)) return;
+    }
+    launch_tile<R, GEOM, GENERAL, 8>(c, a, ngrp, false);
 }
 
 // One transport launch for every frequency group (grid y = group; one group
