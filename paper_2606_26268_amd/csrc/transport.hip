@@ -609,10 +609,11 @@ static int resident_blocks(const void *kern, int block)
 // planes), the 28-64-plane chunks this cost picks without the cap were 4-6 %
 // slower than 16 (fewer blocks to balance, more halo misses in L2); with the
 // cap it lands on the fastest chunk measured or within 3 % of it.
-// Launch with tile height TYB; with single_round, only if the launch then
-// fits in one round of resident blocks (returns whether it launched).
+// Launch with tile height TYB; with max_rounds > 0, only if the launch then
+// takes at most that many rounds of resident blocks (returns whether it
+// launched).
 template <typename R, int GEOM, bool GENERAL, int TYB>
-static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, bool single_round)
+static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, long max_rounds)
 {
     using T = Tile<TYB>;
     constexpr int TX = T::TX, TY = T::TY, NT = T::NT;
@@ -631,7 +632,7 @@ static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, bool single
             rounds = r;
         }
     }
-    if (single_round && rounds > 1) return false;
+    if (max_rounds > 0 && rounds > max_rounds) return false;
     const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
     const int launched = ((nblocks + 7) / 8) * 8;
     hipLaunchKernelGGL((k_transport3d<R, GEOM, GENERAL, TYB>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz,
@@ -639,18 +640,17 @@ static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, bool single
     return true;
 }
 
-// The 32 x 16 tile where its launch fits in one round of resident blocks
-// (the 192x96x192 and 128^3 grids: 1.5-3 % faster transport than 32 x 8),
-// else 32 x 8 (on the 256^3 grid and eight groups at 128^3, launches of
-// several rounds, the taller blocks were 2-4 % slower: they leave a compute
-// unit half idle whenever one of its two blocks finishes).
+// The 32 x 16 tile where its launch takes at most two rounds of resident
+// blocks (the 192x96x192 and 128^3 grids: 1.5-3 % faster transport than
+// 32 x 8), else 32 x 8 (on the 256^3 grid and eight groups at 128^3,
+// launches of four to sixteen rounds, the taller blocks were 2-4 % slower).
 template <typename R, int GEOM, bool GENERAL>
 static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
 {
     if constexpr (!(sizeof(R) == 4 && GENERAL)) {
-        if (launch_tile<R, GEOM, GENERAL, 16>(c, a, ngrp, true)) return;
+        if (launch_tile<R, GEOM, GENERAL, 16>(c, a, ngrp, 2)) return;
     }
-    launch_tile<R, GEOM, GENERAL, 8>(c, a, ngrp, false);
+    launch_tile<R, GEOM, GENERAL, 8>(c, a, ngrp, 0);
 }
 
 // One transport launch for every frequency group (grid y = group; one group
