@@ -27,3 +27,21 @@ def test_documented_counts():
     assert bench.algorithmic_valu_ops("implicit", "mlp") == 1250
     assert bench.algorithmic_valu_ops("transport", "mlp") == 696
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+
+
+def test_form_table():
+    """Every timed form names a precision and a step kind, and the small
+    workloads it times build with the documented shapes."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2606_26268_amd import inputs as I
+    table = bench.form_table(I)
+    assert {"c3_f32_table", "c3_p64_table", "c1_f32_const", "c1_p64_const", "c2_f32_const", "c2_p64_const",
+            "c1_mg8_f32", "c1_mg8_p64", "c3_f32_table_rk2", "c1_mg8_f32_rk2", "c1_f32_general",
+            "p0_pulse_f32_rk2", "p0_pulse_p64_rk2"} <= set(table)
+    for name, (mk, prec, rk2) in table.items():
+        assert prec in ("f32", "p64") and rk2 in (True, False), name
+        assert prec in name and (rk2 == name.endswith("_rk2")), name
+    g = table["c1_f32_general"][0]()
+    assert (g.recon, g.riemann) == (2, 1) and g.bc[0] == [I.REFLECT, I.REFLECT] and g.irr is not None
+    assert g.shape == (128, 128, 128)
