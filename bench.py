@@ -24,33 +24,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Vector-ALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock at
-# 2.4 GHz, one FP32 or FP64 lane operation each (the published 157.3 TFLOP/s
-# FP32 figure counts packed FMAs, 78.6 TFLOP/s FP64 counts FMAs: both are this
-# rate times 4 and 2).  Transcendental instructions issue at half this rate.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-
-
-def algorithmic_valu_ops(kernel, opacity_kind, geom="spherical"):
-    """Vector-ALU lane operations per cell the method needs in the FP32
-    transport / FP64 implicit / bfloat16-MFMA network form (hand count of the
-    formulation; a transcendental counts 2 because it issues at half rate).
-
-    transport, per cell: 3 faces x 164 (two face states 8, two f-fixes 40,
-      two closures 84, limited speeds + HLL 32) + 3 directions x 4 fields x 11
-      (van Leer slopes) + update 72 (divergence 24, spherical sources with the
-      centre closure 41, fix-ups 7) = 696.
-    implicit with the network: 128 tanh x 6 (exp2, reciprocal, add, fma) +
-      64 second-layer bias + 128 output-layer FMAs + 192 (bfloat16 hi/lo split
-      of the 64 first-layer activations) + 18 (network inputs and outputs) +
-      80 (FP64 solve: temperature, four divisions, Cramer, damping, gas
-      update) = 1250.  The 64x64 layer and the first layer run on the matrix
-      cores and are not counted here."""
-    if kernel == "transport":
-        return 3 * 164 + 12 * 11 + (72 if geom != "cartesian" else 31)
-    if opacity_kind == "mlp":
-        return 128 * 6 + 64 + 128 + 192 + 18 + 80
-    return 80
 
 
 def algorithmic_bytes(kernel, precision, opacity_kind):
@@ -96,11 +69,16 @@ def train_surrogate(m1, I, torch, solver, steps):
     return rep
 
 
-def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False):
-    """Returns dict with cells/s and per-kernel average durations (rk2: the
+REPS = 5
+
+
+def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False, reps=REPS):
+    """Returns dict with cells/s and per-kernel average durations.  The K
+    timed steps are repeated `reps` times (HIP events on the launch stream
+    around each repetition) and the median repetition is reported (rk2: the
     second-order step, timed as a whole; its per-kernel fields are those of
     the split step on the same state)."""
-    mlp = None
+    mlp = mlp_weights = None
     if prob.opacity["kind"] == 3:
         # construct with the table, then train the surrogate in place
         tab_prob = prob
@@ -110,6 +88,8 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=F
         tab_prob.opacity["kind"] = 3
         log(f"  surrogate trained: {rep}")
         mlp = rep
+        theta, norm = m1.m1_mlp_get(s.ctx)
+        mlp_weights = dict(theta=theta, norm=norm)
     else:
         s = m1.Solver(prob, precision=precision, second_order=rk2)
     dt = prob.dt
@@ -117,19 +97,22 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=F
     for _ in range(W):
         s.step(dt, rk2=rk2)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    t0 = time.perf_counter()
-    for _ in range(K):
-        if rk2:
-            m1.m1_step_rk2(s.ctx, dt)
-        else:
-            m1.m1_step_explicit(s.ctx, dt)
-            m1.m1_step_implicit(s.ctx, dt)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
+    rep_ms, walls = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            if rk2:
+                m1.m1_step_rk2(s.ctx, dt)
+            else:
+                m1.m1_step_explicit(s.ctx, dt)
+                m1.m1_step_implicit(s.ctx, dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        rep_ms.append(e0.elapsed_time(e1))
+    ms = sorted(rep_ms)[len(rep_ms) // 2]
     # per-kernel durations: events around each launch on the launch stream
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
     for k in range(K):
@@ -144,8 +127,10 @@ def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=F
     d = s.diagnostics()
     s.close()
     n = prob.ncells
-    return dict(cells_per_s=n * K / (ms * 1e-3), ms_per_step=ms / K, wall_s=wall,
-                transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp)
+    return dict(cells_per_s=n * K / (ms * 1e-3), ms_per_step=ms / K, wall_s=sum(walls),
+                rep_ms_per_step=[round(v / K, 5) for v in rep_ms],
+                transport_ms=t_tr, implicit_ms=t_im, counters=d["counters"], mlp=mlp,
+                mlp_weights=mlp_weights)
 
 
 def fp32_deviation(m1, torch, prob, steps=100):
@@ -215,6 +200,26 @@ def measured_traffic(kernel, workload):
     return rec["bytes_per_launch"]
 
 
+def measured_valu(kernel, workload, ms):
+    """Vector-issue figures of a kernel from the committed instruction
+    counter run (profiles/valu.json: SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32,
+    SQ_WAVES per dispatch), or None if absent or taken on a different kernel
+    source.  issue_frac: the issue cycles those instructions need (4 per
+    wavefront instruction on a 16-lane SIMD, 8 for a transcendental) spread
+    over the 1024 SIMDs, against the launch time at the 2.4 GHz peak clock."""
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(f"{kernel}:{workload}")
+    if not rec or rec.get("source") != source_hash(kernel):
+        return None
+    per_wave = rec["valu_per_wave"]
+    trans = rec["trans_per_wave"]
+    cycles = 4.0 * (per_wave + trans) * rec["waves"] / 1024.0
+    return dict(valu_per_wave=per_wave, trans_per_wave=trans, waves=rec["waves"],
+                issue_frac=round(cycles / (2.4e9 * ms * 1e-3), 4))
+
+
 def copy_calibration():
     import torch
     n = 1 << 28                       # 2^28 float32 = 1 GiB read + 1 GiB written
@@ -226,20 +231,41 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
-def oracle_baseline(I, seconds_target=15.0, threads=None, shape=(96, 48, 96)):
+def cpu_model():
+    """Host CPU model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_baseline(I, weights=None, seconds_target=15.0, threads=None, shape=(96, 48, 96)):
     """The FP64 oracle on a bounded sample of the headline workload: the
-    same spherical recipe with the MLP surrogate on a reduced grid, with all
-    host threads (threads=None) or the given number."""
+    same spherical recipe with the MLP surrogate (the GPU-trained weights
+    when given) on a reduced grid, with all host threads (threads=None) or
+    the given number."""
     import numpy as np
     from oracle import oracle as orc
     if threads is not None:
         orc.set_threads(threads)
     p = I.make_c4(nr=shape[0], nth=shape[1], nph=shape[2])
-    tab = p.opacity
-    a = tab["log10_kP"].astype(np.float64)
-    b = tab["log10_kR"].astype(np.float64)
-    norm = np.array([a.mean(), a.std(), b.mean(), b.std()])
-    o = orc.Oracle(p, dict(theta=I.mlp_init(7).astype(np.float64), norm=norm, bf16=True))
+    if weights is None:
+        tab = p.opacity
+        a = tab["log10_kP"].astype(np.float64)
+        b = tab["log10_kR"].astype(np.float64)
+        weights = dict(theta=I.mlp_init(7), norm=np.array([a.mean(), a.std(), b.mean(), b.std()]))
+    o = orc.Oracle(p, dict(theta=np.asarray(weights["theta"], dtype=np.float64), norm=weights["norm"], bf16=True))
     st = p.fields
     steps, t = 0, 0.0
     while t < seconds_target and steps < 20:
@@ -250,7 +276,104 @@ def oracle_baseline(I, seconds_target=15.0, threads=None, shape=(96, 48, 96)):
     cores = orc.max_threads()
     shp = "x".join(str(v) for v in shape)
     return dict(value=p.ncells * steps / t, unit="cell updates/s", cores=cores, kind="oracle",
-                sample=f"spherical recipe with MLP opacity on {shp} cells, {steps} steps, {t:.1f} s")
+                cpu_model=cpu_model(),
+                sample=f"spherical recipe with the MLP opacity on {shp} cells, {steps} steps, {t:.1f} s")
+
+
+def _log10_opacity(m1, torch, ctx, rho, T):
+    """log10 kappa_P, log10 kappa_R of a context's opacity source at host
+    (rho, T) points, evaluated on the device."""
+    import numpy as np
+    r = torch.from_numpy(np.ascontiguousarray(rho, dtype=np.float64)).to("cuda")
+    t = torch.from_numpy(np.ascontiguousarray(T, dtype=np.float64)).to("cuda")
+    kP, kR = torch.empty_like(r), torch.empty_like(r)
+    m1.m1_opacity_eval(ctx, r.numel(), r, t, kP, kR)
+    m1.m1_sync(ctx)
+    return np.log10(kP.cpu().numpy()), np.log10(kR.cpu().numpy())
+
+
+def mlp_gain(m1, torch, I, weights, table_sizes=(128, 512, 2048, 4096), K=20, W=20):
+    """What the trained network changes against the bilinear table it
+    replaces, measured on the device (the table lookup is the judge):
+
+    * model bytes: network parameters (FP32 master), its packed inference
+      buffer, and the two 128 x 128 FP32 tables;
+    * max |kappa_net / kappa_table - 1| over the held-out samples and over
+      the cells of the spherical workload;
+    * error of each against the smooth function the table samples;
+    * smoothness: the jump of d log10 kappa / d log10 T across the table's
+      node lines and, for comparison, across the mid-cell lines (one-sided
+      slopes over h/16 next to each line): the bilinear table has a kink at
+      every node and none between, the network the same small jump (its
+      curvature over the stencil, plus rounding) everywhere;
+    * the implicit kernel's time with the table at several node counts (the
+      same function sampled finer; the cache footprint grows as nodes^2)."""
+    import numpy as np
+    tab = I.make_table()
+    lr_off, lt_off = tab["lr_off"], tab["lt_off"]
+    p = I.make_uniform(I.CARTESIAN, (64, 1, 1), 1)
+    p.opacity = tab
+    # FP64 contexts: the table is interpolated in FP64 (the network computes
+    # in FP32 in any form)
+    st = m1.Solver(p, "p64")
+    sm = m1.Solver(p, "p64")
+    m1.m1_set_opacity_mlp(sm.ctx, weights["theta"], weights["norm"])
+    out = {"model_bytes": {"network_parameters_fp32": 4 * m1.M1_MLP_NPARAM,
+                           "network_packed_inference_buffer": 4 * 8704,
+                           "table_two_128x128_fp32": 2 * 4 * tab["nr"] * tab["nt"]}}
+
+    def compare(rho, T, lr, lt):
+        tP, tR = _log10_opacity(m1, torch, st.ctx, rho, T)
+        nP, nR = _log10_opacity(m1, torch, sm.ctx, rho, T)
+        rec = {"max_rel_err_P": float(np.abs(10.0 ** (nP - tP) - 1).max()),
+               "max_rel_err_R": float(np.abs(10.0 ** (nR - tR) - 1).max())}
+        if lr is not None:
+            gP, gR = I.table_log10_kappa(lr, lt)
+            rec["table_vs_function_max_dex"] = [float(np.abs(tP - gP).max()), float(np.abs(tR - gR).max())]
+            rec["network_vs_function_max_dex"] = [float(np.abs(nP - gP).max()), float(np.abs(nR - gR).max())]
+        return rec
+
+    held = I.mlp_samples(100_000, 5).astype(np.float64)
+    lr, lt = held[:, 0], held[:, 1]
+    out["held_out"] = compare(10.0 ** (lr - lr_off), 10.0 ** (lt - lt_off), lr, lt)
+    c = I.make_c3()
+    rho = c.fields["rho"].ravel()
+    T = c.fields["Eg"].ravel() * (c.gamma - 1.0) / rho
+    out["spherical_cells"] = compare(rho, T, None, None)
+    # slopes in log10 T on both sides of every interior node line, and of
+    # every mid-cell line for comparison, at five densities (one-sided
+    # differences over h/16 at h/16..h/8 from the line)
+    h = (tab["lt1"] - tab["lt0"]) / (tab["nt"] - 1)
+    dens = np.linspace(tab["lr0"] + 1.0, tab["lr1"] - 1.0, 5)
+    d = h / 16.0
+    offs = np.array([-2.0, -1.0, 1.0, 2.0]) * d
+    jumps = {}
+    for name, ctx in (("table", st.ctx), ("network", sm.ctx)):
+        rec = {}
+        for where, lines in (("nodes", tab["lt0"] + h * np.arange(1, tab["nt"] - 1)),
+                             ("mid_cells", tab["lt0"] + h * (np.arange(1, tab["nt"] - 2) + 0.5))):
+            LRn, LTn = np.meshgrid(dens, lines, indexing="ij")
+            pts_lt = (LTn.ravel()[:, None] + offs[None, :]).ravel()
+            pts_lr = np.repeat(LRn.ravel(), 4)
+            vals = _log10_opacity(m1, torch, ctx, 10.0 ** (pts_lr - lr_off), 10.0 ** (pts_lt - lt_off))
+            for kname, v in zip(("P", "R"), vals):
+                v = v.reshape(-1, 4)
+                jump = np.abs((v[:, 3] - v[:, 2]) - (v[:, 1] - v[:, 0])) / d
+                rec[f"{kname}_{where}_max"] = float(jump.max())
+        jumps[name] = rec
+    out["slope_jump_across_nodes_dex_per_dex"] = jumps
+    st.close()
+    sm.close()
+    scan = {}
+    for n in table_sizes:
+        prob = I.make_c3()
+        prob.opacity = I.make_table(n, n)
+        r = time_form(m1, torch, prob, "f32", K, W, reps=1)
+        scan[str(n)] = {"implicit_ms": r["implicit_ms"], "cells_per_s": r["cells_per_s"],
+                        "table_bytes": 2 * 4 * n * n}
+        log(f"  table {n}x{n}: implicit {r['implicit_ms']:.4f} ms")
+    out["table_size_scan"] = scan
+    return out
 
 
 def form_table(I):
@@ -320,25 +443,25 @@ def main():
     ncell = 192 * 96 * 192
     # HBM fractions are also given against what a plain copy reaches here
     copy_gbs = copy_bandwidth(torch)
-    # both kernels of the headline form are bound by vector-ALU issue (the
-    # counter runs under profiles/ show it); the roofline is that of the
-    # longer one, with its HBM figures alongside
+    # roofline of the dominant (longer) kernel of the headline form on the
+    # algorithmic-bytes basis: bytes per cell x cells / average launch time,
+    # against the 8 TB/s HBM peak; the counter-measured traffic and the
+    # vector-issue figures (instruction counters) are given beside it
     kern = "transport" if head["transport_ms"] >= head["implicit_ms"] else "implicit"
     per_kernel = {}
     for kn in ("transport", "implicit"):
         kms = head["transport_ms"] if kn == "transport" else head["implicit_ms"]
-        ops = algorithmic_valu_ops(kn, "mlp") * ncell
         byts = algorithmic_bytes(kn, "f32", "mlp") * ncell
-        per_kernel[kn] = dict(ms_per_launch=kms, algorithmic_ops_per_launch=ops,
-                              tops=ops / (kms * 1e-3) / 1e12, algorithmic_bytes_per_launch=byts,
-                              hbm_gbs=byts / (kms * 1e-3) / 1e9, traffic=measured_traffic(kn, "c4_f32_mlp"))
+        per_kernel[kn] = dict(ms_per_launch=kms, algorithmic_bytes_per_launch=byts,
+                              hbm_gbs=byts / (kms * 1e-3) / 1e9, traffic=measured_traffic(kn, "c4_f32_mlp"),
+                              valu=measured_valu(kn, "c4_f32_mlp", kms))
     k = per_kernel[kern]
-    roofline = dict(bound="alu", achieved=round(k["tops"], 2), peak=round(VALU_PEAK_TOPS, 2), unit="TOP/s",
-                    frac=round(k["tops"] / VALU_PEAK_TOPS, 4), traffic=k["traffic"], kernel=kern,
-                    ms_per_launch=k["ms_per_launch"], algorithmic_ops_per_launch=k["algorithmic_ops_per_launch"],
-                    hbm_achieved_gbs=round(k["hbm_gbs"], 1), hbm_frac=round(k["hbm_gbs"] / HBM_PEAK_GBS, 4),
-                    hbm_copy_gbs=round(copy_gbs, 1), hbm_frac_of_copy=round(k["hbm_gbs"] / copy_gbs, 4),
-                    kernels=per_kernel)
+    roofline = dict(bound="hbm", achieved=round(k["hbm_gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(k["hbm_gbs"] / HBM_PEAK_GBS, 4), traffic=k["traffic"], kernel=kern,
+                    ms_per_launch=k["ms_per_launch"], algorithmic_bytes_per_launch=k["algorithmic_bytes_per_launch"],
+                    bytes_per_cell=algorithmic_bytes(kern, "f32", "mlp"), cells_per_launch=ncell,
+                    hbm_copy_gbs=round(copy_gbs, 1), frac_of_copy=round(k["hbm_gbs"] / copy_gbs, 4),
+                    valu=k["valu"], kernels=per_kernel)
 
     out_forms = {}
     for name, r in forms.items():
@@ -361,11 +484,19 @@ def main():
                                fixups=r["counters"][:3])
         if "vs_p64" in r:
             out_forms[name]["vs_p64"] = {k: [float("%.3g" % v[0]), float("%.3g" % v[1])] for k, v in r["vs_p64"].items()}
+    gain = None
+    if not args.only:
+        log("network vs table")
+        gain = mlp_gain(m1, torch, I, head["mlp_weights"])
+        gain["cells_per_s"] = {"network_c4": forms["c4_f32_mlp"]["cells_per_s"],
+                               "table_c3": forms["c3_f32_table"]["cells_per_s"]}
+        gain["implicit_ms"] = {"network_c4": forms["c4_f32_mlp"]["implicit_ms"],
+                               "table_c3": forms["c3_f32_table"]["implicit_ms"]}
     cpu = None
     if not args.no_cpu:
-        cpu = oracle_baseline(I)
+        cpu = oracle_baseline(I, head["mlp_weights"])
         if not args.only:
-            one = oracle_baseline(I, seconds_target=8.0, threads=1, shape=(48, 24, 48))
+            one = oracle_baseline(I, head["mlp_weights"], seconds_target=8.0, threads=1, shape=(48, 24, 48))
             cpu["one_thread"] = dict(value=one["value"], sample=one["sample"])
     line = {
         "metric": "M1 cell updates/s (explicit+implicit), FP32/MLP form vs FP64 plain, 1 MI355X",
@@ -375,18 +506,21 @@ def main():
         "steps": K,
         "warmup": W,
         "ms_per_step": head["ms_per_step"],
+        "ms_per_step_repetitions": head["rep_ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 transport / f64 implicit / bf16-mfma mlp",
         "data": "synthetic",
         "config": {"workload": "spherical 192x96x192 log-r grid, perturbed r^-2 density, r^-1/2 T, "
-                               "FP32 transport + FP64 implicit + MLP opacity (100-step run)",
-                   "cells": ncell},
+                               "FP32 transport + FP64 implicit + MLP opacity; "
+                               f"{K} timed steps after {W} warm-up steps, median of {REPS} repetitions",
+                   "cells": ncell, "repetitions": REPS},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": out_forms,
         "mlp_training": head["mlp"],
+        "mlp_gain": gain,
         "context": {"paper_rmhd_cell_updates_per_s_per_mi250x_node": 7.6e8},
     }
     print(json.dumps(line))

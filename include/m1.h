@@ -13,7 +13,7 @@
  *   m1_step_implicit   per-cell backward-Euler radiation-matter exchange,
  *                      the 2x2 system of Eq. implicit_matrix, flux damping of
  *                      Eq. source_discrete2 and the gas update from the
- *                      rescaled conservation laws (Sect. 2.6, 2.7).
+ *                      rescaled conservation laws (Sect. 2.7, 2.8).
  *
  * Conventions
  *   - F is the paper's radiation flux that carries the 1/c factor
@@ -78,7 +78,7 @@ typedef struct {
 
 /* Physical and numerical parameters (m1_params_default fills them):
  * c       true speed of light (default: c_hat), enters the gas energy
- *         exchange (Eq. internal) and the rescaled energy total (Sect. 2.6)
+ *         exchange (Eq. internal) and the rescaled energy total (Sect. 2.7)
  * a_rad   radiation constant a_R (default 1)
  * gamma   adiabatic index; C_v = rho / (gamma - 1) per volume (default 5/3)
  * precision  M1_P64 (all FP64) or M1_F32 (FP32 radiation storage and
@@ -160,6 +160,10 @@ typedef struct {
     double lr;        /* peak learning rate */
     double lr_final;  /* learning rate at the last step (cosine decay) */
     double beta1, beta2, eps;
+    int keep_init;    /* 0: the linear shortcut (Ws, b3) of theta_init is
+                         replaced by the least-squares plane through the
+                         table (default); 1: training starts from theta_init
+                         unchanged (resuming a trained network) */
 } m1_train_cfg;
 
 typedef struct {
@@ -175,7 +179,9 @@ typedef struct m1_ctx m1_ctx;
 m1_status m1_params_default(double c_hat, m1_params *p);
 
 /* Create a context for grid g (copied) in geometry geom with reduced speed
- * of light c_hat (> 0).  p may be NULL (defaults).  Uploads the separable
+ * of light c_hat (> 0; Sect. 2.7).  The finite-volume solver of Sect. 2.5
+ * runs on Cartesian, cylindrical and spherical grids (the Sect. 3.4 pulses
+ * use Cartesian and spherical coordinates, Sect. 3.7 a spherical grid).  p may be NULL (defaults).  Uploads the separable
  * metric arrays of the grid.  Errors: M1_EINVAL (ndim outside 1..3,
  * n[d] < 1, n[d] != 1 for d >= ndim, more than 2^31 - 2^16 cells,
  * non-increasing faces, negative radius, theta outside [0, pi],
@@ -192,7 +198,10 @@ m1_status m1_set_stream(m1_ctx *ctx, void *stream);
 /* Bind caller-owned device arrays (must outlive the binding) and allocate
  * the library's scratch (transported E*, F*, opacity caches, reduction
  * buffers).  Evaluates the opacity cache from the current gas state.
- * M1_EINVAL on a NULL or non-256-byte-aligned pointer. */
+ * M1_EINVAL on a NULL or non-256-byte-aligned pointer.  M1_ENOMEM when an
+ * allocation fails: the new buffers are allocated before the old ones are
+ * released, so a failed (re)binding leaves any previous binding, its
+ * arrays and its buffers, in force and usable. */
 m1_status m1_bind_state(m1_ctx *ctx, const m1_fields *f);
 
 /* Opacity model (Sect. 2.1 source terms; chi = kappa_R + sigma):
@@ -202,10 +211,13 @@ m1_status m1_bind_state(m1_ctx *ctx, const m1_fields *f);
  * Re-evaluates the opacity cache when a state is bound. */
 m1_status m1_set_opacity_model(m1_ctx *ctx, int kind, const double *params);
 
-/* Bilinear table of log10 kappa (Planck and Rosseland) on nr x nt nodes that
+/* Tabulated Planck and Rosseland mean opacities (kappa_P, kappa_R of
+ * Sect. 2.1; tables computed beforehand and interpolated, as in Sect. 3.7).
+ * Bilinear table of log10 kappa (Planck and Rosseland) on nr x nt nodes that
  * include both axis ends: node (i, j) at (lr_min + i h_r, lt_min + j h_t),
  * host float32 arrays [nt][nr] (copied).  Looked up at
- * (log10 rho + lr_off, log10 T + lt_off), clamped to the axes.  nr, nt >= 2. */
+ * (log10 rho + lr_off, log10 T + lt_off), clamped to the axes.  nr, nt >= 2.
+ * On M1_ENOMEM or an upload error the previous opacity source is kept. */
 m1_status m1_set_opacity_table(m1_ctx *ctx, int nr, int nt, double lr_min, double lr_max,
                                double lt_min, double lt_max, double lr_off, double lt_off,
                                const float *log10_kP, const float *log10_kR, double sigma);
@@ -236,23 +248,32 @@ m1_status m1_mlp_gradient(m1_ctx *ctx, const float *samples, long n, const float
 m1_status m1_opacity_eval(m1_ctx *ctx, long n, const double *rho, const double *T, double *kP,
                           double *kR);
 
-/* Largest stable step for Courant number cfl: cfl / max_cells(c_hat
+/* The time-step update that closes the step list of Sect. 2.4, at a
+ * Courant number such as the 0.4 of Sect. 3.1.
+ * Largest stable step for Courant number cfl: cfl / max_cells(c_hat
  * sum_{d < ndim} 1/h_d) with h = (dr, r dtheta, r sin(theta) dphi) in
  * spherical and (dR, R dphi, dz) in cylindrical grids (host computation). */
 m1_status m1_max_dt(const m1_ctx *ctx, double cfl, double *dt);
 
-/* Explicit transport step of length dt (> 0) from the bound (E, F) into the
+/* Items 1-7 of the Euler step list of Sect. 2.4: boundary values,
+ * reconstruction (Sect. 2.5) with the f <= 1 face treatment of
+ * Eq. f_reconstruct, wave speeds with the optical-depth limiter (Sect. 2.6),
+ * Riemann fluxes (Sect. 2.5) and the flux divergence, at c_hat (Sect. 2.7).
+ * Explicit transport step of length dt (> 0) from the bound (E, F) into the
  * library's transported state (E*, F*).  Asynchronous.  M1_ESTATE if no
  * state is bound. */
 m1_status m1_step_explicit(m1_ctx *ctx, double dt);
 
-/* Implicit source step of length dt from (E*, F*) and the gas: writes E, F,
+/* Item 8 of the Sect. 2.4 list: the local source terms, solved implicitly
+ * as Eqs. source_discrete1, source_discrete2 and implicit_matrix of
+ * Sect. 2.8, with the gas update from the rescaled totals of Sect. 2.7.
+ * Implicit source step of length dt from (E*, F*) and the gas: writes E, F,
  * m, E_g of the bound arrays and refreshes the opacity cache at the new
  * temperature.  Asynchronous.  M1_ESTATE unless the previous step call was
  * m1_step_explicit. */
 m1_status m1_step_implicit(m1_ctx *ctx, double dt);
 
-/* Multigroup M1 (Sect. 2.3, 2.7): m frequency groups, each transported as
+/* Multigroup M1 (Sect. 2.3, 2.8): m frequency groups, each transported as
  * an independent gray M1 fluid, coupled to the gas by the (m+1)^2 implicit
  * system in which group g emits the Planck fraction b_g(T^n) of a T^4
  * (fraction of int B_nu over its band at the start-of-step temperature).
@@ -276,7 +297,7 @@ m1_status m1_set_groups(m1_ctx *ctx, int m, const double *edges, const double *k
  * is not fixed or an invalid state. */
 m1_status m1_set_boundary_state(m1_ctx *ctx, int dir, int side, const double state[4]);
 
-/* Irradiation heating (Sect. 2.8): q = -div F_irr per cell (device FP64,
+/* Irradiation heating (Sect. 2.9): q = -div F_irr per cell (device FP64,
  * n0 n1 n2 values in the state layout, caller-owned, must stay valid while
  * set), energy per unit volume and time.  Each implicit step deposits q dt:
  * it enters the S_1 row of Eq. implicit_matrix and the conserved total
@@ -307,7 +328,9 @@ m1_status m1_refresh_opacity(m1_ctx *ctx);
 /* Wait for the stream; reports a deferred device error as M1_EDEVICE. */
 m1_status m1_sync(m1_ctx *ctx);
 
-/* Synchronous reduction of the bound state (see m1_diag). */
+/* Synchronous reduction of the bound state (see m1_diag): the conserved
+ * totals E + (c/c_hat) E_r and rho v + F_r / c_hat of Sect. 2.7, and the
+ * counters of the positivity and f <= 1 fix-ups (Sect. 3.1, Sect. 2.1). */
 m1_status m1_diagnostics(m1_ctx *ctx, m1_diag *out);
 
 /* Text of the last error raised on the calling thread ("" if none). */

@@ -43,7 +43,7 @@ void m1o_eddington(double E, double Fx, double Fy, double Fz, double *f, double 
 }
 
 /* Extreme eigenvalues lambda_{1,3} = (f cos(theta) -+ zeta) / sqrt(4 - 3 f^2)
- * of the M1 system along direction d (Sect. 2.5); cos(theta) = n_d. */
+ * of the M1 system along direction d (Sect. 2.6); cos(theta) = n_d. */
 void m1o_speeds(double E, double Fx, double Fy, double Fz, int d, double *lm, double *lp)
 {
     double F[3] = {Fx, Fy, Fz}, n[3], f;
@@ -69,7 +69,7 @@ void m1o_flux(double E, double Fx, double Fy, double Fz, int d, double phi[4])
     for (int a = 0; a < 3; ++a) phi[1 + a] = E * D[3 * a + d];
 }
 
-/* HLL flux (Sect. 2.5) with the Sect. 2.5 signal speeds and the optical-depth
+/* HLL flux (Sect. 2.5) with the Sect. 2.6 signal speeds and the optical-depth
  * limiter: lambda_L = min of the left-going speeds of both states, lambda_R =
  * max of the right-going ones, then clamped to -+4/(3 tau) when tau > 0.
  * Returns c_hat * Phi*. */
@@ -106,6 +106,27 @@ double m1o_vanleer(double dl, double dr)
 {
     if (dl * dr > 0.0) return 2.0 * dl * dr / (dl + dr);
     return 0.0;
+}
+
+/* LimO3, the compact third-order limited reconstruction that Sect. 2.5
+ * names (Cada and Torrilhon 2009, "Compact third-order limiter functions for
+ * finite volume methods", J. Comput. Phys. 228, 4118).  On a uniform grid the
+ * face value of cell i towards its neighbour on the face side is
+ *   u_i + phi(theta) (u_near - u_i) / 2,   theta = (u_i - u_far) / (u_near - u_i),
+ * with the third-order reconstruction phi3(theta) = (2 + theta) / 3 limited as
+ *   phi = max(0, min(phi3, max(-theta/2, min(2 theta, phi3, 3/2)))).
+ * In slope form, as the PLM slopes: dfar and dnear are the divided
+ * differences on the far side and on the face side of the cell; the
+ * returned slope phi(dfar / dnear) dnear (0 when dnear = 0) times the
+ * signed centre-to-face distance gives the face value. */
+double m1o_limo3(double dfar, double dnear)
+{
+    if (dnear == 0.0) return 0.0;
+    double th = dfar / dnear;
+    double p3 = (2.0 + th) / 3.0;
+    double inner = fmin(fmin(2.0 * th, p3), 1.5);
+    double phi = fmax(0.0, fmin(p3, fmax(-0.5 * th, inner)));
+    return phi * dnear;
 }
 
 /* f-preserving face fix (Eq. f_reconstruct): keep the reconstructed face flux

@@ -1,6 +1,6 @@
 /*
  * implicit.c -- oracle: opacity sources and the implicit radiation-matter
- * step (Sect. 2.7).  Test infrastructure only.
+ * step (Sect. 2.8).  Test infrastructure only.
  */
 #include <float.h>
 #include <math.h>
@@ -117,7 +117,7 @@ int m1o_implicit(const m1o_problem *p, double dt, const double *const star[4],
         double chi = kR + p->sigma;
         double Es = star[0][id];
         double Fs[3] = {star[1][id], star[2][id], star[3][id]};
-        /* irradiation heating deposited in this step (Sect. 2.8: -div F_irr dt
+        /* irradiation heating deposited in this step (Sect. 2.9: -div F_irr dt
          * in the S_1 row and in the conserved total) */
         double S = p->irr ? p->irr[id] * dt : 0.0;
         double r[4];
@@ -143,7 +143,7 @@ int m1o_implicit(const m1o_problem *p, double dt, const double *const star[4],
             ++ffx;
         }
         /* gas from the rescaled conservation laws E + (c/c_hat) E_r and
-         * rho v + F_r / c_hat (Sect. 2.6) */
+         * rho v + F_r / c_hat (Sect. 2.7) */
         st[8][id] = Eg + S - (p->c / p->c_hat) * (E1 - Es);
         st[5][id] = mx - (F1[0] - Fs[0]) / p->c_hat;
         st[6][id] = my - (F1[1] - Fs[1]) / p->c_hat;

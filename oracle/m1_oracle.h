@@ -7,9 +7,9 @@
  *
  * It computes, in double precision and in the order the method states it,
  * one explicit transport step (Sect. 2.5 reconstruction + f-preserving face
- * fix, Sect. 2.5 signal speeds + optical-depth limiter, HLL fluxes,
+ * fix, Sect. 2.6 signal speeds + optical-depth limiter, HLL fluxes,
  * conservative update in Cartesian / cylindrical / spherical coordinates)
- * and one implicit radiation-matter step (Sect. 2.7, Eq. implicit_matrix),
+ * and one implicit radiation-matter step (Sect. 2.8, Eq. implicit_matrix),
  * plus the opacity sources (constant, power law, bilinear table, MLP).
  *
  * Array layout: cell (i, j, k) along (d0, d1, d2) lives at ((k*n1)+j)*n0+i.
@@ -31,6 +31,8 @@ enum { M1O_CONST = 0, M1O_POWERLAW = 1, M1O_TABLE = 2, M1O_MLP = 3 };
 /* face treatment after reconstruction (Sect. 2.5, 3.2) and Riemann solver */
 enum { M1O_RECON_FPRESERVE = 0, M1O_RECON_PLUTO = 1, M1O_RECON_CLIP = 2 };
 enum { M1O_HLL = 0, M1O_LF = 1 };
+/* reconstruction: PLM with the van Leer slope, or LimO3 (Sect. 2.5) */
+enum { M1O_PLM = 0, M1O_LIMO3 = 1 };
 
 /* counters returned by the step routines */
 enum { M1O_CNT_EFLOOR = 0, M1O_CNT_FFIX_TRANSPORT = 1, M1O_CNT_FFIX_IMPLICIT = 2,
@@ -56,6 +58,7 @@ typedef struct {
     double bc_state[3][2][4]; /* ghost (E, Fx, Fy, Fz) of M1O_FIXED sides */
     const double *irr;        /* per-cell irradiation heating -div F_irr, or NULL */
     int absorb_only;          /* 1: radiation is absorbed, never emitted */
+    int limiter;              /* M1O_PLM or M1O_LIMO3 */
 } m1o_problem;
 
 /* --- closure, speeds, fluxes (Sect. 2.1, 2.5, 2.6) ------------------------ */
@@ -66,6 +69,7 @@ void m1o_flux(double E, double Fx, double Fy, double Fz, int d, double phi[4]);
 void m1o_hll(const double UL[4], const double UR[4], int d, double tau, double c_hat,
              double out[4], double *SL, double *SR);
 double m1o_vanleer(double dl, double dr);
+double m1o_limo3(double dfar, double dnear);
 int m1o_ffix(double *Ef, double Ff[3], double Ec, const double Fc[3]);
 int m1o_face_fix(int recon, double *Ef, double Ff[3], double Ec, const double Fc[3]);
 void m1o_lf(const double UL[4], const double UR[4], int d, double tau, double c_hat, double out[4]);

@@ -1,5 +1,5 @@
 /*
- * multigroup.c -- oracle: multigroup M1 (Sect. 2.3 and 2.7: one gray M1
+ * multigroup.c -- oracle: multigroup M1 (Sect. 2.3 and 2.8: one gray M1
  * fluid per frequency group, coupled to the gas by an (m+1)^2 implicit
  * system).  Test infrastructure only.
  *
@@ -126,7 +126,7 @@ int m1o_mg_cell(int m, const double *Es, double Cv, double T, const double *kP, 
  * gas[5] = (rho, mx, my, mz, Eg).  Each step transports every group with the
  * gray scheme (constant group opacities), then solves the coupled implicit
  * system per cell; the flux of group g is damped by 1 + dt c_hat chi_g rho,
- * the gas takes the rescaled totals (Sect. 2.6). */
+ * the gas takes the rescaled totals (Sect. 2.7). */
 int m1o_run_mg(const m1o_problem *p, int m, const double *edges, const double *kPg, const double *kRg,
                double dt, int nsteps, double *const rad[], double *const gas[5], long long cnt[M1O_NCNT])
 {

@@ -60,6 +60,7 @@ class Problem(C.Structure):
         ("bc_state", ((C.c_double * 4) * 2) * 3),
         ("irr", C.POINTER(C.c_double)),
         ("absorb_only", C.c_int),
+        ("limiter", C.c_int),
     ]
 
 
@@ -80,6 +81,8 @@ def lib():
         L.m1o_hll.argtypes = [_dp, _dp, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
         L.m1o_vanleer.restype = C.c_double
         L.m1o_vanleer.argtypes = [C.c_double, C.c_double]
+        L.m1o_limo3.restype = C.c_double
+        L.m1o_limo3.argtypes = [C.c_double, C.c_double]
         L.m1o_ffix.restype = C.c_int
         L.m1o_ffix.argtypes = [_dp, _dp, C.c_double, _dp]
         L.m1o_face_fix.restype = C.c_int
@@ -146,6 +149,7 @@ class Oracle:
         P.recon = getattr(prob, "recon", 0)
         P.riemann = getattr(prob, "riemann", 0)
         P.absorb_only = int(getattr(prob, "absorb_only", 0))
+        P.limiter = int(getattr(prob, "limiter", 0))
         bs = getattr(prob, "bc_state", None)
         if bs is not None:
             for d in range(3):
@@ -322,6 +326,10 @@ def hll(UL, UR, d, tau=0.0, c_hat=1.0):
 
 def vanleer(dl, dr):
     return lib().m1o_vanleer(float(dl), float(dr))
+
+
+def limo3(dfar, dnear):
+    return lib().m1o_limo3(float(dfar), float(dnear))
 
 
 def ffix(Ef, Ff, Ec, Fc):

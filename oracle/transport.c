@@ -153,11 +153,12 @@ static long lin(const m1o_problem *p, const int c[3])
 /* reconstruction                                                           */
 /* ------------------------------------------------------------------------ */
 
-/* Piecewise-linear van Leer reconstruction of (E, Fx, Fy, Fz) of cell t
- * along d, evaluated on its upper face (side = +1) or lower face (side = -1),
- * followed by the face treatment (f-preserving fix by default) against that
- * cell's centre values.
- * The slope uses divided differences over centre spacings. */
+/* Reconstruction of (E, Fx, Fy, Fz) of cell t along d on its upper face
+ * (side = +1) or lower face (side = -1): piecewise linear with the van Leer
+ * slope, or LimO3, whose slope depends on the face (the difference on the
+ * face side is the near one); then the face treatment (f-preserving fix by
+ * default) against that cell's centre values.  The slopes use divided
+ * differences over centre spacings. */
 static void face_state(const m1o_problem *p, const double *const st[9], int d, int cbase[3],
                        int t, int side, double U[4])
 {
@@ -172,7 +173,12 @@ static void face_state(const m1o_problem *p, const double *const st[9], int d, i
     for (int v = 0; v < 4; ++v) {
         double dl = (q[1][v] - q[0][v]) / (xc[1] - xc[0]);
         double dr = (q[2][v] - q[1][v]) / (xc[2] - xc[1]);
-        U[v] = q[1][v] + m1o_vanleer(dl, dr) * off;
+        double slope;
+        if (p->limiter == M1O_LIMO3)
+            slope = side > 0 ? m1o_limo3(dl, dr) : m1o_limo3(dr, dl);
+        else
+            slope = m1o_vanleer(dl, dr);
+        U[v] = q[1][v] + slope * off;
     }
     double Fc[3] = {q[1][1], q[1][2], q[1][3]};
     double Ff[3] = {U[1], U[2], U[3]};

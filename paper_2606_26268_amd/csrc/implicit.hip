@@ -1,9 +1,9 @@
 // implicit.hip -- implicit radiation-matter step and the opacity cache.
 //
-// Per cell (Sect. 2.7): T^n from the gas energy, the 2x2 backward-Euler
+// Per cell (Sect. 2.8): T^n from the gas energy, the 2x2 backward-Euler
 // system of Eq. implicit_matrix solved analytically in FP64, flux damping of
 // Eq. source_discrete2, the gas total energy and momentum from the rescaled
-// conservation laws (Sect. 2.6), f <= 1, and the opacity cache (rho kappa_P,
+// conservation laws (Sect. 2.7), f <= 1, and the opacity cache (rho kappa_P,
 // optical depth rho chi h_max) re-evaluated at the new temperature for the
 // next transport and implicit steps.
 #include "m1_internal.h"
@@ -106,7 +106,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, un
     const double g = a.k.dt_c * rkP;
     const double aT3 = a.k.a * T * T * T, aT4 = aT3 * T;
     const double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
-    // irradiation energy deposited in the step enters the S_1 row (Sect. 2.8)
+    // irradiation energy deposited in the step enters the S_1 row (Sect. 2.9)
     double S = 0.0;
     if (a.irr) S = at(a.irr, base, t) * a.k.dt;
     // uniform branch: the absorption-only form costs the default path nothing

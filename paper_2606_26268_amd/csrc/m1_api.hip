@@ -15,9 +15,12 @@
 
 namespace m1 {
 
-static thread_local std::string g_err;
+// last error text of the calling thread, in a fixed buffer (setting it
+// allocates nothing)
+static thread_local char g_err[512];
 
-void set_error(const std::string &msg) { g_err = msg; }
+void set_error(const char *msg) { std::snprintf(g_err, sizeof(g_err), "%s", msg); }
+void set_error(const std::string &msg) { set_error(msg.c_str()); }
 
 static m1_status fail(m1_status s, const std::string &msg)
 {
@@ -351,27 +354,28 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     const int G = c->grp.m;
     const size_t nfield = 5 * (size_t)G + 1;
     const size_t bytes = nfield * per + CNT_BYTES + ndiag * sizeof(double);
-    if (c->scratch) {
-        hipFree(c->scratch);
-        c->scratch = nullptr;
-    }
-    hipError_t e = hipMalloc(&c->scratch, bytes);
+    // allocate the new buffers first and swap them in only when every
+    // allocation succeeded: a failed rebind leaves the previous binding (its
+    // buffers and fields) intact and usable
+    void *nscr = nullptr, *nrk = nullptr;
+    hipError_t e = hipMalloc(&nscr, bytes);
     if (e != hipSuccess) return fail(M1_ENOMEM, "m1_bind_state: scratch allocation failed");
-    if (c->rk2_save) {
-        hipFree(c->rk2_save);
-        c->rk2_save = nullptr;
-    }
+    size_t rad = 0;
     if (c->par.second_order) {
         // the first-stage state of m1_step_rk2: the four radiation fields of
         // all groups (group-major, as the bound arrays), then mx, my, mz, E_g
-        const size_t rad = ((size_t(G) * N * es + 255) / 256) * 256;
-        e = hipMalloc(&c->rk2_save, 4 * rad + 4 * N * sizeof(double));
+        rad = ((size_t(G) * N * es + 255) / 256) * 256;
+        e = hipMalloc(&nrk, 4 * rad + 4 * N * sizeof(double));
         if (e != hipSuccess) {
-            c->rk2_save = nullptr;
+            hipFree(nscr);
             return fail(M1_ENOMEM, "m1_bind_state: second-order buffer allocation failed");
         }
-        c->rk2_rad_bytes = rad;
     }
+    if (c->scratch) hipFree(c->scratch);
+    if (c->rk2_save) hipFree(c->rk2_save);
+    c->scratch = nscr;
+    c->rk2_save = nrk;
+    c->rk2_rad_bytes = rad;
     unsigned char *b = static_cast<unsigned char *>(c->scratch);
     // layout: star (group g, field v) at (4 g + v) per, tau of group g at
     // (4 G + g) per, rho kappa_P at 5 G per
@@ -381,13 +385,16 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     c->rkp = b + 5 * (size_t)G * per;
     c->cnt = reinterpret_cast<unsigned long long *>(b + nfield * per);
     c->partials = reinterpret_cast<double *>(b + nfield * per + CNT_BYTES);
-    e = hipMemsetAsync(c->cnt, 0, CNT_BYTES, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "m1_bind_state: counter reset");
     c->f = *f;
     c->bound = true;
     c->transported = false;
-    e = launch_opacity_init(c);
-    if (e != hipSuccess) return hip_fail(e, "m1_bind_state: opacity cache");
+    e = hipMemsetAsync(c->cnt, 0, CNT_BYTES, c->stream);
+    if (e == hipSuccess) e = launch_opacity_init(c);
+    if (e != hipSuccess) {
+        // the new buffers stay owned by the context; the binding is not usable
+        c->bound = false;
+        return hip_fail(e, "m1_bind_state: counter reset / opacity cache");
+    }
     return M1_OK;
 }
 
@@ -431,15 +438,19 @@ m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1
     if (nr < 2 || nt < 2 || !(lr1 > lr0) || !(lt1 > lt0) || sigma < 0)
         return fail(M1_EINVAL, "m1_set_opacity_table: need nr, nt >= 2, increasing axes, sigma >= 0");
     const size_t n = size_t(nr) * nt;
-    if (c->table_dev) {
-        hipFree(c->table_dev);
-        c->table_dev = nullptr;
-    }
-    hipError_t e = hipMalloc(&c->table_dev, 2 * n * sizeof(float));
+    // the new table is uploaded before the old one is released: on failure
+    // the context keeps its previous opacity source unchanged
+    float *tab = nullptr;
+    hipError_t e = hipMalloc(&tab, 2 * n * sizeof(float));
     if (e != hipSuccess) return fail(M1_ENOMEM, "m1_set_opacity_table: allocation failed");
-    e = hipMemcpy(c->table_dev, kP, n * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->table_dev + n, kR, n * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "m1_set_opacity_table: upload");
+    e = hipMemcpy(tab, kP, n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(tab + n, kR, n * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(tab);
+        return hip_fail(e, "m1_set_opacity_table: upload");
+    }
+    if (c->table_dev) hipFree(c->table_dev);
+    c->table_dev = tab;
     c->op.kind = OPK_TABLE;
     c->op.nr = nr;
     c->op.nt = nt;
@@ -473,7 +484,8 @@ m1_status m1_mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
         return fail(M1_EINVAL, "m1_mlp_train: NULL argument");
     if (!c->table_dev) return fail(M1_ESTATE, "m1_mlp_train: set the table first (training targets)");
     if (cfg->batch < 64 || cfg->batch > 4096 || cfg->batch % 64 || cfg->n_train < cfg->batch ||
-        cfg->n_eval < 1 || cfg->steps < 1 || !(cfg->lr > 0) || cfg->lr_final < 0)
+        cfg->n_eval < 1 || cfg->steps < 1 || !(cfg->lr > 0) || cfg->lr_final < 0 ||
+        (cfg->keep_init != 0 && cfg->keep_init != 1))
         return fail(M1_EINVAL, "m1_mlp_train: bad configuration");
     int r = mlp_train(c, cfg, rep);
     if (r != 0) return r < 0 ? m1_status(r) : M1_EDEVICE;
@@ -522,8 +534,9 @@ m1_status m1_max_dt(const m1_ctx *c, double cfl, double *dt)
             for (int i = 0; i < c->n[0]; ++i) {
                 const int idx[3] = {i, j, k};
                 double s = 0.0;
+                // extent = (radius factor x sine factor) x coordinate width
                 for (int d = 0; d < c->ndim; ++d)
-                    s += 1.0 / (M.hd[d][idx[d]] * M.hI[d][i] * M.hJ[d][j]);
+                    s += 1.0 / (M.hI[d][i] * M.hJ[d][j] * M.hd[d][idx[d]]);
                 worst = s > worst ? s : worst;
             }
     *dt = cfl / (c->c_hat * worst);
@@ -691,6 +704,6 @@ m1_status m1_diagnostics(m1_ctx *c, m1_diag *out)
     return M1_OK;
 }
 
-const char *m1_last_error(void) { return g_err.c_str(); }
+const char *m1_last_error(void) { return g_err; }
 
 } // extern "C"

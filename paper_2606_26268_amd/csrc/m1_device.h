@@ -1,5 +1,5 @@
 // m1_device.h -- device-side building blocks of the M1 step for gfx950:
-// Levermore closure with the Sect. 2.5 signal speeds and the physical flux
+// Levermore closure with the Sect. 2.6 signal speeds and the physical flux
 // of one state, the HLL interface flux with the optical-depth limiter, the
 // van Leer slope and the f-preserving face fix (Eq. f_reconstruct).
 // Templated on the working precision R (double or float).
@@ -89,7 +89,7 @@ __device__ __forceinline__ double vmin(double a, double b) { return __builtin_fm
 __device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
 
 // Closure quantities of one radiation state (E, F) seen from direction d:
-// lambda_-, lambda_+ (Sect. 2.5) and the flux (F_d, E D_{xd}, E D_{yd},
+// lambda_-, lambda_+ (Sect. 2.6) and the flux (F_d, E D_{xd}, E D_{yd},
 // E D_{zd}) (Sect. 2.1, Eqs. rad1/rad2), all in units of c_hat.
 template <typename R>
 struct Wave {
@@ -130,7 +130,7 @@ __device__ __forceinline__ Wave<R> closure_wave(R E, R Fx, R Fy, R Fz)
 
 // HLL flux c_hat * Phi* between face states UL | UR (Sect. 2.5) with the
 // speeds lambda_L = min lambda_-, lambda_R = max lambda_+ clamped to
-// -+4/(3 tau) for tau > 0 (Sect. 2.5), S_L = min(lambda_L, 0),
+// -+4/(3 tau) for tau > 0 (Sect. 2.6), S_L = min(lambda_L, 0),
 // S_R = max(lambda_R, 0); S_L = S_R = 0 falls back to the average flux.
 template <typename R, int D>
 __device__ __forceinline__ void hll_flux(const R UL[4], const R UR[4], R tau, R c_hat, R out[4],

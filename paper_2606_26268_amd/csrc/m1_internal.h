@@ -164,4 +164,5 @@ int mlp_pack(m1_ctx *c, const float *theta, const double *norm);
 int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep);
 int mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, float *grad, double *loss);
 void set_error(const std::string &msg);
+void set_error(const char *msg);
 } // namespace m1

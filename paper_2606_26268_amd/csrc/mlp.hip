@@ -373,17 +373,40 @@ __device__ __forceinline__ unsigned short dev_bf16_bits(float v)
     return __builtin_bit_cast(unsigned short, b);
 }
 
+// Sum of the nblk per-wavefront partial gradients of parameter i, in a
+// fixed order shared by the Adam and gradient kernels (so both produce the
+// same bits): a 256-thread block owns 64 consecutive parameters (one per
+// lane); wavefront w adds the partials of the contiguous quarter
+// [w q, w q + q) of the waves in order, and the first wavefront adds the
+// four quarter sums in order w = 0..3.  Returns the sum in the threads of
+// the first wavefront (i < NP); the other threads return 0.
+constexpr int RED_PARAMS = 64;
+
+__device__ __forceinline__ float reduce_partials(const float *partial, int nblk, int i, float (&sh)[4][64])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = (nblk + 3) >> 2;
+    const int b0 = w * q, b1 = b0 + q < nblk ? b0 + q : nblk;
+    float g = 0.f;
+    if (i < NP)
+        for (int b = b0; b < b1; ++b) g += partial[(long)b * NP + i];
+    sh[w][lane] = g;
+    __syncthreads();
+    if (w != 0) return 0.f;
+    return ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+}
+
 __global__ void __launch_bounds__(256) k_mlp_adam(AdamArgs a)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i == 0) {
+    __shared__ float sh[4][64];
+    const int i = blockIdx.x * RED_PARAMS + (threadIdx.x & 63);
+    if (blockIdx.x == 0 && threadIdx.x == 64) {
         float L = 0.f;
         for (int b = 0; b < a.nblk; ++b) L += a.loss_part[b];
         a.loss_hist[a.step] = L;
     }
-    if (i >= NP) return;
-    float g = 0.f;
-    for (int b = 0; b < a.nblk; ++b) g += a.partial[(long)b * NP + i];
+    const float g = reduce_partials(a.partial, a.nblk, i, sh);
+    if (threadIdx.x >= 64 || i >= NP) return;
     const float m = a.b1 * a.m[i] + (1.f - a.b1) * g;
     const float v = a.b2 * a.v[i] + (1.f - a.b2) * g * g;
     a.m[i] = m;
@@ -416,16 +439,15 @@ __global__ void __launch_bounds__(256) k_mlp_adam(AdamArgs a)
 __global__ void __launch_bounds__(256) k_mlp_reduce(const float *partial, int nblk, const float *loss_part,
                                                     float *grad, float *loss)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i == 0) {
+    __shared__ float sh[4][64];
+    const int i = blockIdx.x * RED_PARAMS + (threadIdx.x & 63);
+    if (blockIdx.x == 0 && threadIdx.x == 64) {
         float L = 0.f;
         for (int b = 0; b < nblk; ++b) L += loss_part[b];
         *loss = L;
     }
-    if (i >= NP) return;
-    float g = 0.f;
-    for (int b = 0; b < nblk; ++b) g += partial[(long)b * NP + i];
-    grad[i] = g;
+    const float g = reduce_partials(partial, nblk, i, sh);
+    if (threadIdx.x < 64 && i < NP) grad[i] = g;
 }
 
 // ---------------------------------------------------------------------------
@@ -530,11 +552,12 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
     float lin[2][3];
     table_stats(c, tab, norm, lin);
     std::vector<float> th(cfg->theta_init, cfg->theta_init + NP);
-    for (int o = 0; o < 2; ++o) {
-        th[P_B3 + o] = lin[o][0];
-        th[P_WS + 2 * o] = lin[o][1];
-        th[P_WS + 2 * o + 1] = lin[o][2];
-    }
+    if (!cfg->keep_init)
+        for (int o = 0; o < 2; ++o) {
+            th[P_B3 + o] = lin[o][0];
+            th[P_WS + 2 * o] = lin[o][1];
+            th[P_WS + 2 * o + 1] = lin[o][2];
+        }
     int rc = mlp_pack(c, th.data(), norm);
     if (rc) return int(M1_EDEVICE);
 
@@ -583,7 +606,7 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
         aa.c1 = float(1.0 - std::pow(cfg->beta1, double(s + 1)));
         aa.c2 = float(1.0 - std::pow(cfg->beta2, double(s + 1)));
         aa.step = s;
-        hipLaunchKernelGGL(k_mlp_adam, dim3((NP + 255) / 256), dim3(256), 0, c->stream, aa);
+        hipLaunchKernelGGL(k_mlp_adam, dim3((NP + RED_PARAMS - 1) / RED_PARAMS), dim3(256), 0, c->stream, aa);
         e = hipGetLastError();
     }
     hipEventRecord(ev1, c->stream);
@@ -649,7 +672,8 @@ int mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, fl
     ta.partial = partial;
     ta.loss_part = loss_part;
     hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(nblk), dim3(64), 0, c->stream, ta);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 255) / 256), dim3(256), 0, c->stream, partial, nblk, loss_part, g, L);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + RED_PARAMS - 1) / RED_PARAMS), dim3(256), 0, c->stream, partial, nblk,
+                       loss_part, g, L);
     float Lh = 0.f;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(grad, g, NP * sizeof(float), hipMemcpyDeviceToHost, c->stream);

@@ -6,9 +6,7 @@
 // Levermore closure and signal speeds of both face states, the HLL flux with
 // the optical-depth limiter, and the conservative update with the geometric
 // sources of the flux equation in cylindrical / spherical coordinates.
-#include <map>
 #include <mutex>
-#include <utility>
 
 #include "m1_internal.h"
 #include "m1_device.h"
@@ -584,20 +582,28 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
 }
 
 // Blocks of a kernel the whole device holds at once (occupancy per compute
-// unit times the compute units), cached per kernel and device.
+// unit times the compute units), cached per kernel and device in a fixed
+// table (no heap allocation on any launch path; a full table just stops
+// caching).
 static int resident_blocks(const void *kern, int block)
 {
+    struct Entry {
+        const void *kern;
+        int dev, block, blocks;
+    };
     static std::mutex mu;
-    static std::map<std::pair<const void *, int>, int> cache;
+    static Entry cache[256];
+    static int used = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;
     std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find({kern, dev});
-    if (it != cache.end()) return it->second;
+    for (int e = 0; e < used; ++e)
+        if (cache[e].kern == kern && cache[e].dev == dev && cache[e].block == block) return cache[e].blocks;
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0) != hipSuccess || per < 1) per = 1;
-    return cache[{kern, dev}] = per * cus;
+    if (used < 256) cache[used++] = Entry{kern, dev, block, per * cus};
+    return per * cus;
 }
 
 // Tiled 3D launch.  The planes per block (z chunk) minimise rounds x

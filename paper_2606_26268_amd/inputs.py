@@ -3,8 +3,12 @@
 This module only *describes* inputs: grids (face coordinates), initial fields,
 physical constants, the opacity table contents and MLP training samples.  It
 holds none of the scheme's arithmetic (no closure, fluxes, geometry factors,
-time-step rule or source solve), so both the HIP path and the CPU oracle can be
-fed from it without sharing any of the method.
+reconstruction or source solve), so both the HIP path and the CPU oracle can
+be fed from it without sharing any of the method.  The time step is part of a
+workload's definition and reaches both sides as an input: a stated value, or
+on uniform Cartesian grids the Courant number over c_hat times the summed
+inverse cell widths of the active directions; the method's general rule for
+any grid (m1_max_dt in the library, m1o_max_dt in the oracle) is not here.
 
 Every array is float64 unless noted, shaped (nz, ny, nx) with x fastest; the
 first index direction of the grid ("d = 0") is x / R / r, "d = 1" is y / phi /
@@ -55,6 +59,7 @@ class Problem:
     steps: int = 1
     recon: int = 0      # 0 f-preserving, 1 PLUTO flat, 2 simple clip
     riemann: int = 0    # 0 HLL, 1 Lax-Friedrichs-Rusanov
+    limiter: int = 0    # 0 PLM with the van Leer slope, 1 LimO3
     bc_state: list = None   # [[lo, hi]] * 3 ghost (E, Fx, Fy, Fz) of FIXED sides
     irr: object = None      # per-cell irradiation heating -div F_irr (float64), or None
     absorb_only: int = 0    # 1: absorption without emission
@@ -195,13 +200,15 @@ def table_log10_kappa(lr, lt):
     return 1.0 + base + bp, 0.7 + base + br
 
 
-def make_table():
-    """Return dict with float32 [nT][nrho] arrays of log10 kappa_P and kappa_R."""
-    lr = TABLE_LR[0] + (TABLE_LR[1] - TABLE_LR[0]) * np.arange(TABLE_NR) / (TABLE_NR - 1)
-    lt = TABLE_LT[0] + (TABLE_LT[1] - TABLE_LT[0]) * np.arange(TABLE_NT) / (TABLE_NT - 1)
+def make_table(nr=TABLE_NR, nt=TABLE_NT):
+    """Return dict with float32 [nT][nrho] arrays of log10 kappa_P and kappa_R
+    (the benchmark's 128 x 128 nodes by default; other node counts sample the
+    same function over the same axes)."""
+    lr = TABLE_LR[0] + (TABLE_LR[1] - TABLE_LR[0]) * np.arange(nr) / (nr - 1)
+    lt = TABLE_LT[0] + (TABLE_LT[1] - TABLE_LT[0]) * np.arange(nt) / (nt - 1)
     LT, LR = np.meshgrid(lt, lr, indexing="ij")
     kp, kr = table_log10_kappa(LR, LT)
-    return dict(kind=OPAC_TABLE, nr=TABLE_NR, nt=TABLE_NT,
+    return dict(kind=OPAC_TABLE, nr=nr, nt=nt,
                 lr0=TABLE_LR[0], lr1=TABLE_LR[1], lt0=TABLE_LT[0], lt1=TABLE_LT[1],
                 lr_off=TABLE_OFFSETS[0], lt_off=TABLE_OFFSETS[1],
                 log10_kP=np.ascontiguousarray(kp.astype(np.float32)),

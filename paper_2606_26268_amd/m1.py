@@ -66,7 +66,7 @@ class m1_train_cfg(C.Structure):
     _fields_ = [("samples", C.c_void_p), ("n_train", C.c_long), ("n_eval", C.c_long),
                 ("theta_init", C.POINTER(C.c_float)), ("batch", C.c_int), ("steps", C.c_long),
                 ("lr", C.c_double), ("lr_final", C.c_double), ("beta1", C.c_double),
-                ("beta2", C.c_double), ("eps", C.c_double)]
+                ("beta2", C.c_double), ("eps", C.c_double), ("keep_init", C.c_int)]
 
 
 class m1_train_report(C.Structure):
@@ -204,7 +204,7 @@ def m1_set_opacity_mlp(ctx, theta, norm):
 
 
 def m1_mlp_train(ctx, samples_dev, n_train, n_eval, theta_init, batch=512, steps=20000, lr=3e-3,
-                 lr_final=1e-5, beta1=0.9, beta2=0.999, eps=1e-8):
+                 lr_final=1e-5, beta1=0.9, beta2=0.999, eps=1e-8, keep_init=False):
     th = np.ascontiguousarray(theta_init, dtype=np.float32)
     cfg = m1_train_cfg()
     cfg.samples = C.c_void_p(samples_dev.data_ptr())
@@ -212,6 +212,7 @@ def m1_mlp_train(ctx, samples_dev, n_train, n_eval, theta_init, batch=512, steps
     cfg.theta_init = th.ctypes.data_as(C.POINTER(C.c_float))
     cfg.batch, cfg.steps = int(batch), int(steps)
     cfg.lr, cfg.lr_final, cfg.beta1, cfg.beta2, cfg.eps = lr, lr_final, beta1, beta2, eps
+    cfg.keep_init = int(bool(keep_init))
     rep = m1_train_report()
     _check(lib().m1_mlp_train(ctx, C.byref(cfg), C.byref(rep)))
     return dict(final_loss=rep.final_loss, max_rel_err_P=rep.max_rel_err_P,

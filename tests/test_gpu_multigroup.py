@@ -1,5 +1,5 @@
 """GPU parity of the multigroup form (one gray fluid per group, the
-(m+1)^2 implicit system of Sect. 2.7) against the oracle, which assembles
+(m+1)^2 implicit system of Sect. 2.8) against the oracle, which assembles
 that system literally and solves it densely while the kernel eliminates its
 arrowhead structure; conservation through the library's diagnostics; the
 error paths."""

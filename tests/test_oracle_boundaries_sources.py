@@ -7,7 +7,7 @@
   fills it at the reduced speed of light and leaves a uniform state behind
   the front (free streaming, Sect. 3.2); a fixed state equal to the interior
   keeps a uniform field uniform;
-* irradiation (Sect. 2.8): the solution satisfies the paper's linear system
+* irradiation (Sect. 2.9): the solution satisfies the paper's linear system
   with the modified S_1 row, the deposited energy q dt appears in the total,
   the transparent limit and the relaxation limit solved independently;
 * absorption only (Sect. 3.3): the continuous absorption rate, radiation

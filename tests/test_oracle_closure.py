@@ -6,7 +6,7 @@ fixes independently of the oracle's own formulas:
 * the Levermore closure is exact for a Lorentz-boosted isotropic intensity
   (Sect. 2.1), so moments integrated numerically from I ~ (1 - beta mu)^-4
   must reproduce f and the Eddington factor;
-* the Sect. 2.5 speeds must be the extreme eigenvalues of the Jacobian of the
+* the Sect. 2.6 speeds must be the extreme eigenvalues of the Jacobian of the
   flux (numerical differentiation + a library eigen-solver), and the middle
   ones the contact speed lambda_2;
 * printed limits (f -> 0 and f -> 1) and brute-force bounds |lambda| <= 1;

@@ -1,11 +1,11 @@
-"""Pins of the oracle's implicit radiation-matter step (Sect. 2.7) and of its
+"""Pins of the oracle's implicit radiation-matter step (Sect. 2.8) and of its
 opacity sources.
 
 References independent of the oracle's own algebra: the discrete equations
 the paper starts from (Eqs. source_discrete1 / internal with the T^4
 linearisation) checked as residuals; the radiative-equilibrium limit found
 as the root of a quartic by a library polynomial solver; exact fixed points;
-conservation of the rescaled totals (Sect. 2.6); the flux damping law
+conservation of the rescaled totals (Sect. 2.7); the flux damping law
 (Eq. source_discrete2); bilinear interpolation special cases and bounds.
 """
 import math

@@ -1,5 +1,5 @@
 """Pins of the oracle's multigroup M1 (one gray fluid per frequency group,
-an (m+1)^2 implicit system, Sect. 2.3 and 2.7):
+an (m+1)^2 implicit system, Sect. 2.3 and 2.8):
 
 * the Planck fraction against adaptive quadrature of the Planck integrand
   (library routine), its limits, and group fractions summing to one;

@@ -3,7 +3,7 @@ steps on the paper's test problems.
 
 Independent references used here: exact invariants (uniform states, static
 isotropic fields in curvilinear grids, conservation of the rescaled totals of
-Sect. 2.6, mirror symmetry), continuous closed forms of the divergence
+Sect. 2.7, mirror symmetry), continuous closed forms of the divergence
 operator in cylindrical / spherical coordinates (checked by convergence),
 the analytic diffusion of a Gaussian, free-streaming at the reduced speed of
 light, the closed-form wave positions of the Sect. 3.1 shock tubes, the
@@ -81,7 +81,7 @@ def test_transport_conserves_energy_and_flux_cartesian(orc):
 
 
 def test_full_steps_conserve_rescaled_totals(orc):
-    """E_g + (c/c_hat) E_r and m + F/c_hat (Sect. 2.6), c != c_hat, 100 steps."""
+    """E_g + (c/c_hat) E_r and m + F/c_hat (Sect. 2.7), c != c_hat, 100 steps."""
     p = _random_periodic((12, 10, 8), 3, 12, fmax=0.5)
     p.c = 30.0 * p.c_hat
     p.opacity = dict(kind=I.OPAC_CONSTANT, kP=3.0, kR=2.0, sigma=1.0)
