@@ -59,6 +59,12 @@ typedef struct {
     const double *irr;        /* per-cell irradiation heating -div F_irr, or NULL */
     int absorb_only;          /* 1: radiation is absorbed, never emitted */
     int limiter;              /* M1O_PLM or M1O_LIMO3 */
+    /* test use only: random perturbation of every reconstructed face value
+     * by face_noise x (|u_cell| + |slope x offset|) x w, w uniform in
+     * [-1, 1) from a counter-based hash of noise_seed and the face (0 = off);
+     * models the rounding of face values computed in lower precision */
+    double face_noise;
+    unsigned long long noise_seed;
 } m1o_problem;
 
 /* --- closure, speeds, fluxes (Sect. 2.1, 2.5, 2.6) ------------------------ */

@@ -140,6 +140,7 @@ int m1o_run_mg(const m1o_problem *p, int m, const double *edges, const double *k
         for (int g = 0; g < m; ++g) {
             pg.kP = kPg[g];
             pg.kR = kRg[g];
+            pg.noise_seed = p->noise_seed + (unsigned long long)s * 4096u + (unsigned long long)g;
             const double *in[9] = {rad[4 * g], rad[4 * g + 1], rad[4 * g + 2], rad[4 * g + 3],
                                    gas[0], gas[1], gas[2], gas[3], gas[4]};
             double *out[4] = {star + (4 * g) * N, star + (4 * g + 1) * N, star + (4 * g + 2) * N,

@@ -61,6 +61,8 @@ class Problem(C.Structure):
         ("irr", C.POINTER(C.c_double)),
         ("absorb_only", C.c_int),
         ("limiter", C.c_int),
+        ("face_noise", C.c_double),
+        ("noise_seed", C.c_ulonglong),
     ]
 
 

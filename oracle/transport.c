@@ -153,6 +153,26 @@ static long lin(const m1o_problem *p, const int c[3])
 /* reconstruction                                                           */
 /* ------------------------------------------------------------------------ */
 
+/* SplitMix64 output function (Steele, Lea and Flood 2014): a counter-based
+ * generator, so the value for a given key is the same in every thread. */
+static unsigned long long splitmix64(unsigned long long x)
+{
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* uniform in [-1, 1) for the face value of field v of cell (c with index t
+ * along d) on side `side`, under seed */
+static double face_noise_unit(unsigned long long seed, int d, int side, int t, const int c[3], int v)
+{
+    unsigned long long k = splitmix64(seed);
+    const long long parts[7] = {d, side, t + 2, c[0], c[1], c[2], v};
+    for (int i = 0; i < 7; ++i) k = splitmix64(k ^ (unsigned long long)parts[i]);
+    return (double)(k >> 11) * (1.0 / 4503599627370496.0) - 1.0;
+}
+
 /* Reconstruction of (E, Fx, Fy, Fz) of cell t along d on its upper face
  * (side = +1) or lower face (side = -1): piecewise linear with the van Leer
  * slope, or LimO3, whose slope depends on the face (the difference on the
@@ -179,6 +199,9 @@ static void face_state(const m1o_problem *p, const double *const st[9], int d, i
         else
             slope = m1o_vanleer(dl, dr);
         U[v] = q[1][v] + slope * off;
+        if (p->face_noise > 0.0)
+            U[v] += p->face_noise * (fabs(q[1][v]) + fabs(slope * off)) *
+                    face_noise_unit(p->noise_seed, d, side, t, c, v);
     }
     double Fc[3] = {q[1][1], q[1][2], q[1][3]};
     double Ff[3] = {U[1], U[2], U[3]};
@@ -329,8 +352,10 @@ int m1o_run(const m1o_problem *p, double dt, int nsteps, double *const st[9],
     double *buf = malloc(4 * N * sizeof(double));
     if (!buf) return -1;
     double *star[4] = {buf, buf + N, buf + 2 * N, buf + 3 * N};
+    m1o_problem q = *p;
     for (int s = 0; s < nsteps; ++s) {
-        if (m1o_explicit(p, dt, (const double *const *)st, star, cnt)) { free(buf); return -1; }
+        q.noise_seed = p->noise_seed + (unsigned long long)s;
+        if (m1o_explicit(&q, dt, (const double *const *)st, star, cnt)) { free(buf); return -1; }
         if (m1o_implicit(p, dt, (const double *const *)star, st, cnt)) { free(buf); return -1; }
     }
     free(buf);

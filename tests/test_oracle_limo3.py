@@ -1,0 +1,175 @@
+"""Pins of the oracle's LimO3 reconstruction (the compact third-order
+limited reconstruction that Sect. 2.5 names, after Cada and Torrilhon 2009)
+and of the scheme with it on the Sect. 3.1 shock tubes.
+
+Independent references: the textbook third-order reconstruction
+(2 u_{i+1} + 5 u_i - u_{i-1}) / 6 that LimO3 reduces to on smooth monotone
+data; the order of accuracy of face values from exact cell averages of a
+smooth function (third order, against second for PLM); the range property
+of the reconstruction (a face value never leaves the interval between the
+cell and its neighbour on that side) by brute force; third-order accuracy
+of the whole semi-discrete transport operator on a smooth state; and the
+paper's printed behaviour at the discontinuities of the first shock tube
+(LimO3 overshoots more than PLM) and its N^-1/2 convergence rate.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2606_26268_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _face_values(orc, ubar, h, limiter):
+    """Upper face values of periodic cell averages on a uniform grid."""
+    dl = (ubar - np.roll(ubar, 1)) / h
+    dr = (np.roll(ubar, -1) - ubar) / h
+    if limiter == "limo3":
+        s = np.array([orc.limo3(a, b) for a, b in zip(dl, dr)])
+    else:
+        s = np.array([orc.vanleer(a, b) for a, b in zip(dl, dr)])
+    return ubar + 0.5 * h * s
+
+
+def _smooth(x):
+    return 1.0 + 0.2 * np.sin(2 * np.pi * x) + 0.1 * np.cos(4 * np.pi * x)
+
+
+def _smooth_antiderivative(x):
+    return x - 0.2 / (2 * np.pi) * np.cos(2 * np.pi * x) + 0.1 / (4 * np.pi) * np.sin(4 * np.pi * x)
+
+
+def _cell_averages(N):
+    f = np.arange(N + 1) / N
+    return (_smooth_antiderivative(f[1:]) - _smooth_antiderivative(f[:-1])) * N, f
+
+
+def test_reduces_to_the_third_order_formula(orc):
+    """Where 0.4 <= theta <= 2.5 (smooth monotone data) no limiting applies
+    and the face value is the unlimited third-order one."""
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        um, u0 = rng.normal(size=2)
+        th = rng.uniform(0.4, 2.5)
+        dnear = rng.choice([-1, 1]) * rng.uniform(0.1, 3.0)
+        up = u0 + dnear
+        dfar = th * dnear
+        um = u0 - dfar
+        face = u0 + 0.5 * orc.limo3(dfar, dnear)          # unit spacing
+        assert face == pytest.approx((2 * up + 5 * u0 - um) / 6, rel=1e-13, abs=1e-13)
+
+
+def test_face_value_stays_between_cell_and_neighbour(orc):
+    """Brute force over random triples: the face value lies between the
+    cell's value and its face-side neighbour's (and is the cell's own value
+    where the far-side difference outweighs the near one twice against
+    it, theta <= -2)."""
+    rng = np.random.default_rng(4)
+    for _ in range(20000):
+        dfar, dnear = rng.normal(size=2) * rng.choice([1e-3, 1.0, 1e3], size=2)
+        off = 0.5
+        u0 = rng.normal()
+        face = u0 + orc.limo3(dfar, dnear) * off
+        nb = u0 + dnear
+        assert min(u0, nb) - 1e-12 * abs(nb) <= face <= max(u0, nb) + 1e-12 * abs(nb)
+        if dfar / dnear <= -2:
+            assert face == u0
+
+
+def test_face_values_are_third_order_on_smooth_data(orc):
+    """Face values from the exact cell averages of a smooth periodic
+    function: mean error ~ h^3 with LimO3, ~ h^2 with PLM's van Leer slope."""
+    Ns = [32, 64, 128, 256, 512]
+    errs = {"limo3": [], "plm": []}
+    for N in Ns:
+        ubar, f = _cell_averages(N)
+        exact = _smooth(f[1:])
+        for lim in errs:
+            errs[lim].append(np.abs(_face_values(orc, ubar, 1.0 / N, lim) - exact).mean())
+    rate = {k: np.polyfit(np.log(Ns), np.log(v), 1)[0] for k, v in errs.items()}
+    assert rate["limo3"] < -2.7, (rate, errs)
+    assert -2.3 < rate["plm"] < -1.7, (rate, errs)
+    assert errs["limo3"][-1] < 0.1 * errs["plm"][-1]
+
+
+def _smooth_derivative(x):
+    return 0.4 * np.pi * np.cos(2 * np.pi * x) - 0.4 * np.pi * np.sin(4 * np.pi * x)
+
+
+def _operator_error(orc, N, limiter):
+    """Explicit transport operator on a smooth periodic state with F = f E x^
+    (f = 0.3; with F parallel to E the face fix keeps every reconstructed
+    face): mean |(E* - E)/dt + d<F>/dx| against the exact cell average of the
+    flux divergence, c_hat = 1, over the cells away from the extrema of E
+    (|E'| above a fifth of its maximum).  At an extremum the limiter takes
+    the face value to first order there (theta < -2 or the near difference
+    vanishing), so the divergence of those one or two cells is only first
+    order; the published switch to the unlimited formula near smooth extrema
+    needs a scale parameter the paper does not give and is not used."""
+    ubar, f = _cell_averages(N)
+    p = I.make_uniform(I.CARTESIAN, (N, 1, 1), 1, bc=I.PERIODIC, c_hat=1.0)
+    p.limiter = 1 if limiter == "limo3" else 0
+    p.fields["E"][0, 0] = ubar
+    p.fields["Fx"][0, 0] = 0.3 * ubar
+    dt = 1e-3 / N
+    star, _ = orc.Oracle(p).explicit(p.fields, dt)
+    rate = (star["E"][0, 0] - ubar) / dt
+    exact = -0.3 * (_smooth(f[1:]) - _smooth(f[:-1])) * N
+    xc = 0.5 * (f[1:] + f[:-1])
+    away = np.abs(_smooth_derivative(xc)) > 0.2 * 0.4 * np.pi * 1.6
+    return np.abs(rate - exact)[away].mean()
+
+
+def test_transport_operator_order(orc):
+    Ns = [128, 256, 512, 1024]
+    r = {}
+    for lim in ("limo3", "plm"):
+        e = [_operator_error(orc, N, lim) for N in Ns]
+        r[lim] = np.polyfit(np.log(Ns), np.log(e), 1)[0]
+    assert r["limo3"] < -2.6, r
+    assert -2.4 < r["plm"] < -1.6, r
+
+
+def _tube(orc, which, N, limiter):
+    p = I.make_shock_tube(which, N=N)
+    p.limiter = limiter
+    out, cnt = orc.Oracle(p).run(p.fields, p.dt, p.steps, rk2=True)
+    x = 0.5 * (p.faces[0][1:] + p.faces[0][:-1])
+    return x, out, cnt
+
+
+def test_limo3_overshoots_more_than_plm_at_the_left_shock(orc):
+    """Sect. 3.1, first tube at 2^8 cells: near the left-facing shock LimO3
+    overshoots the solution more than PLM does (the paper's zoomed panels).
+    Measured as the excess of E and F_y over the finest reference's largest
+    value in the window around the shock."""
+    ref = np.load(os.path.join(GOLDEN, "shock_tube_reference_1.npz"))
+    N = 256
+    over = {}
+    for lim in (0, 1):
+        x, out, cnt = _tube(orc, 1, N, lim)
+        assert (cnt[:3] == 0).all()
+        win = (x > -13.0) & (x < -9.0)
+        rec = {}
+        for k in ("E", "Fy"):
+            r = ref[k].reshape(N, -1).mean(axis=1)
+            rec[k] = out[k][0, 0][win].max() - r[win].max()
+        over[lim] = rec
+    for k in ("E", "Fy"):
+        assert over[1][k] > 1.1 * over[0][k] > 0, over
+
+
+@pytest.mark.parametrize("which", [1, 2])
+def test_limo3_shock_tube_convergence_rate(orc, which):
+    """L1(E) ~ N^-1/2 with LimO3 as well (Sect. 3.1), against the PLM
+    reference at 2^15 cells."""
+    Er = np.load(os.path.join(GOLDEN, f"shock_tube_reference_{which}.npz"))["E"]
+    Ns = [32, 64, 128, 256, 512, 1024]
+    errs = []
+    for N in Ns:
+        _, out, _ = _tube(orc, which, N, 1)
+        errs.append(np.abs(out["E"][0, 0] - Er.reshape(N, -1).mean(axis=1)).mean())
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert -0.65 <= slope <= -0.35, (slope, errs)

@@ -302,21 +302,22 @@ def test_shock_tube_2_stays_realisable(orc):
     assert E.min() > 0 and (F <= E * (1 + 1e-14)).all()
 
 
-@pytest.mark.slow
 @pytest.mark.parametrize("which", [1, 2])
 def test_shock_tube_convergence_rate(orc, which):
-    """L1(E) ~ N^-1/2 (Sect. 3.1) against the oracle's own finest run."""
-    Nref = 8192
-    _, xr, ref, _ = _tube(orc, which, Nref)
-    Er = ref["E"][0, 0]
-    Ns = [64, 128, 256, 512, 1024]
+    """L1(E) ~ N^-1/2 (Sect. 3.1): as the paper's resolution study, second-
+    order steps at Courant number 0.4 from 2^5 to 2^10 cells against a PLM
+    run of the oracle at 2^15 cells (stored averages,
+    tests/golden/make_shock_tube_reference.py; the paper's reference has
+    2^17 cells)."""
+    Er = np.load(os.path.join(GOLDEN, f"shock_tube_reference_{which}.npz"))["E"]
+    Ns = [32, 64, 128, 256, 512, 1024]
     errs = []
     for N in Ns:
-        _, x, out, _ = _tube(orc, which, N)
-        coarse = Er.reshape(N, Nref // N).mean(axis=1)
-        errs.append(np.abs(out["E"][0, 0] - coarse).mean())
+        p = I.make_shock_tube(which, N=N)
+        out, _ = orc.Oracle(p).run(p.fields, p.dt, p.steps, rk2=True)
+        errs.append(np.abs(out["E"][0, 0] - Er.reshape(N, -1).mean(axis=1)).mean())
     slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
-    assert -0.8 <= slope <= -0.35, (slope, errs)
+    assert -0.65 <= slope <= -0.35, (slope, errs)
 
 
 def test_spherical_pulse_decays_as_inverse_r_squared(orc):
