@@ -305,6 +305,28 @@ m1_status m1_set_boundary_state(m1_ctx *ctx, int dir, int side, const double sta
  * the array between steps as the paper's user function does. */
 m1_status m1_set_irradiation(m1_ctx *ctx, const double *q);
 
+/* Allocation-free step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one Euler step, the work of m1_step_explicit then
+ * m1_step_implicit, of the gray state in the caller's arrays f (layout and
+ * precision as for m1_bind_state; caller-owned, 256-byte aligned, updated
+ * in place), with the step's buffers (transported state, opacity cache,
+ * fix-up counters) in a static device array of M1_NOALLOC_MAX_BYTES that
+ * the library holds on each device it runs on until the process ends and
+ * that every context on that device shares.  The opacity cache is
+ * evaluated from the gas state at the start of the call, so the result is
+ * that of m1_bind_state(f) followed by one explicit and one implicit step.
+ * The context needs no bound state and its own binding is left as it was.
+ * A grid of N cells needs 6 ceil256(N s) + 32768 bytes (s = 4 in M1_F32, 8
+ * in M1_P64): up to about 5.5e6 cells in M1_F32 and 2.7e6 in M1_P64; larger
+ * grids return M1_EINVAL.  Nothing carries over from one call to the next
+ * (the counters are cleared by a kernel, not a memset); calls that overlap
+ * on one device (several streams or host threads) race on the shared array.
+ * Asynchronous on the context's stream.  M1_ENOTSUP for multigroup
+ * contexts, M1_ESTATE when a fixed boundary has no state. */
+#define M1_NOALLOC_MAX_BYTES (128u << 20)
+m1_status m1_step_noalloc(m1_ctx *ctx, const m1_fields *f, double dt);
+
 /* Second-order Runge-Kutta step of length dt built from the split step as in
  * Sect. 2.4 (every sub-step is transport then sources): U1 = S(T(U^n)),
  * U2 = S(T(U1)), U^{n+1} = (U^n + U2) / 2 for E, F (every group), m and

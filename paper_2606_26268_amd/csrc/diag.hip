@@ -126,6 +126,21 @@ static hipError_t launch_d(m1_ctx *c, double out[8])
     return hipStreamSynchronize(c->stream);
 }
 
+// zero n 64-bit words with a kernel (a memset node is not recorded for
+// callers that capture the stream into a graph)
+__global__ void __launch_bounds__(256) k_zero_words(unsigned long long *p, size_t n)
+{
+    const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_zero_words(unsigned long long *p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_words, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_diag(m1_ctx *c, double out[8])
 {
     if (c->par.precision == M1_F32) return launch_d<float>(c, out);

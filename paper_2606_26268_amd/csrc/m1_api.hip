@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -228,6 +229,42 @@ static size_t elem_size(const m1_ctx *c) { return c->par.precision == M1_F32 ? 4
 
 static long ncells(const m1_ctx *c) { return (long)c->n[0] * c->n[1] * c->n[2]; }
 
+// --------------------------------------------------------------------------
+// static buffer of the allocation-free step
+// --------------------------------------------------------------------------
+
+// One copy per device, held by every device that loads the library until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// a device address: its device address is looked up once per device
+// (noalloc_setup, from m1_create with that device current) and only that
+// pointer is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[M1_NOALLOC_MAX_BYTES];
+
+constexpr int NOALLOC_DEVICES = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[NOALLOC_DEVICES] = {};
+static hipError_t g_noalloc_err[NOALLOC_DEVICES] = {};
+static bool g_noalloc_done[NOALLOC_DEVICES] = {};
+
+static void noalloc_setup(int dev)
+{
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_done[dev]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_noalloc_err[dev] = e;
+    g_noalloc_ptr[dev] = e == hipSuccess ? p : nullptr;
+    g_noalloc_done[dev] = true;
+}
+
+static void *noalloc_ptr(int dev)
+{
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    return g_noalloc_done[dev] ? g_noalloc_ptr[dev] : nullptr;
+}
+
 } // namespace m1
 
 using namespace m1;
@@ -307,6 +344,7 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
         c->faces[d].assign(g->faces[d], g->faces[d] + g->n[d] + 1);
     }
     hipGetDevice(&c->device);
+    noalloc_setup(c->device);
     c->op.kind = OPK_CONST;
     HostMetric M;
     build_metric(c, M);
@@ -625,6 +663,82 @@ m1_status m1_step_implicit(m1_ctx *c, double dt)
     hipError_t e = launch_implicit(c, dt);
     if (e != hipSuccess) return hip_fail(e, "m1_step_implicit launch");
     c->transported = false;
+    return M1_OK;
+}
+
+m1_status m1_step_noalloc(m1_ctx *c, const m1_fields *f, double dt)
+{
+    // no allocation on any path: errors are literal or formatted into a
+    // stack buffer, the launchers keep their own state in fixed tables
+    if (!c || !f) {
+        set_error("m1_step_noalloc: NULL argument");
+        return M1_EINVAL;
+    }
+    const void *ptrs[9] = {f->E, f->Fx, f->Fy, f->Fz, f->rho, f->mx, f->my, f->mz, f->Eg};
+    for (int a = 0; a < 9; ++a)
+        if (!aligned(ptrs[a])) {
+            set_error("m1_step_noalloc: NULL or non-256-byte-aligned pointer");
+            return M1_EINVAL;
+        }
+    if (!(dt > 0) || !std::isfinite(dt)) {
+        set_error("m1_step_noalloc: dt must be > 0");
+        return M1_EINVAL;
+    }
+    if (c->grp.m > 1) {
+        set_error("m1_step_noalloc: gray states only (no frequency groups)");
+        return M1_ENOTSUP;
+    }
+    if (!fixed_states_ready(c)) {
+        set_error("m1_step_noalloc: a fixed boundary has no state");
+        return M1_ESTATE;
+    }
+    const size_t per = ((size_t(ncells(c)) * elem_size(c) + 255) / 256) * 256;
+    const size_t need = 6 * per + CNT_BYTES;
+    if (need > size_t(M1_NOALLOC_MAX_BYTES)) {
+        char msg[160];
+        std::snprintf(msg, sizeof(msg), "m1_step_noalloc: the grid needs %zu bytes of scratch, the static buffer holds %zu",
+                      need, size_t(M1_NOALLOC_MAX_BYTES));
+        set_error(msg);
+        return M1_EINVAL;
+    }
+    unsigned char *base = static_cast<unsigned char *>(noalloc_ptr(c->device));
+    if (!base) {
+        set_error("m1_step_noalloc: the static scratch buffer has no device address on this device");
+        return M1_EDEVICE;
+    }
+    // the launchers read the binding from the context: point it at the
+    // caller's arrays and the static buffer for this call, then restore it
+    const m1_fields f0 = c->f;
+    void *const star0[4] = {c->star[0], c->star[1], c->star[2], c->star[3]};
+    void *const tau0 = c->tau, *const rkp0 = c->rkp;
+    unsigned long long *const cnt0 = c->cnt;
+    const size_t plane0 = c->plane_bytes;
+    const bool bound0 = c->bound, transported0 = c->transported;
+    c->f = *f;
+    for (int v = 0; v < 4; ++v) c->star[v] = base + v * per;
+    c->tau = base + 4 * per;
+    c->rkp = base + 5 * per;
+    c->cnt = reinterpret_cast<unsigned long long *>(base + 6 * per);
+    c->plane_bytes = per;
+    // the counters start at zero; everything else is written before it is read
+    hipError_t e = launch_zero_words(c->cnt, CNT_BYTES / sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) e = launch_opacity_init(c);
+    if (e == hipSuccess) e = launch_transport(c, dt);
+    if (e == hipSuccess) e = launch_implicit(c, dt);
+    c->f = f0;
+    for (int v = 0; v < 4; ++v) c->star[v] = star0[v];
+    c->tau = tau0;
+    c->rkp = rkp0;
+    c->cnt = cnt0;
+    c->plane_bytes = plane0;
+    c->bound = bound0;
+    c->transported = transported0;
+    if (e != hipSuccess) {
+        char msg[160];
+        std::snprintf(msg, sizeof(msg), "m1_step_noalloc launch: %s", hipGetErrorString(e));
+        set_error(msg);
+        return M1_EDEVICE;
+    }
     return M1_OK;
 }
 

@@ -165,4 +165,5 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep);
 int mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, float *grad, double *loss);
 void set_error(const std::string &msg);
 void set_error(const char *msg);
+hipError_t launch_zero_words(unsigned long long *p, size_t n, hipStream_t s);
 } // namespace m1

@@ -79,7 +79,7 @@ EXPORTS = ("m1_params_default", "m1_create", "m1_destroy", "m1_set_stream", "m1_
            "m1_set_opacity_model", "m1_set_opacity_table", "m1_set_opacity_mlp", "m1_mlp_train",
            "m1_mlp_get", "m1_mlp_gradient", "m1_opacity_eval", "m1_max_dt", "m1_step_explicit", "m1_step_implicit", "m1_step_rk2",
            "m1_transported", "m1_refresh_opacity", "m1_sync", "m1_diagnostics", "m1_last_error",
-           "m1_set_boundary_state", "m1_set_irradiation", "m1_set_groups")
+           "m1_set_boundary_state", "m1_set_irradiation", "m1_set_groups", "m1_step_noalloc")
 
 _lib = None
 
@@ -109,6 +109,7 @@ def lib():
             "m1_step_explicit": [vp, C.c_double],
             "m1_step_implicit": [vp, C.c_double],
             "m1_step_rk2": [vp, C.c_double],
+            "m1_step_noalloc": [vp, C.POINTER(m1_fields), C.c_double],
             "m1_transported": [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)],
             "m1_refresh_opacity": [vp],
             "m1_sync": [vp],
@@ -279,6 +280,15 @@ def m1_step_implicit(ctx, dt):
 
 def m1_step_rk2(ctx, dt):
     _check(lib().m1_step_rk2(ctx, float(dt)))
+
+
+def m1_step_noalloc(ctx, tensors, dt):
+    """One step of the state in `tensors` (E, Fx, Fy, Fz, rho, mx, my, mz,
+    Eg device tensors, updated in place) with the library's static buffer."""
+    f = m1_fields()
+    for k in ("E", "Fx", "Fy", "Fz", "rho", "mx", "my", "mz", "Eg"):
+        setattr(f, k, C.c_void_p(tensors[k].data_ptr()))
+    _check(lib().m1_step_noalloc(ctx, C.byref(f), float(dt)))
 
 
 def m1_transported(ctx):
