@@ -64,6 +64,10 @@ typedef enum { M1_OPAC_CONSTANT = 0, M1_OPAC_POWERLAW = 1 } m1_opacity_model;
 /* face treatment after reconstruction (Sect. 2.5; compared in Sect. 3.2) */
 typedef enum { M1_RECON_FPRESERVE = 0, M1_RECON_PLUTO = 1, M1_RECON_CLIP = 2 } m1_recon;
 typedef enum { M1_RIEMANN_HLL = 0, M1_RIEMANN_LF = 1 } m1_riemann;
+/* reconstruction of the face states (Sect. 2.5): piecewise linear with the
+ * van Leer slope (PLM), or the compact third-order LimO3 of Cada and
+ * Torrilhon (2009) */
+typedef enum { M1_LIMITER_PLM = 0, M1_LIMITER_LIMO3 = 1 } m1_limiter;
 
 /* Grid: ndim active directions (1..3); n[d] interior cells (n[d] = 1 for an
  * inactive direction); faces[d] = n[d]+1 strictly increasing coordinates
@@ -98,7 +102,13 @@ typedef struct {
  *         absorbed energy going to the gas
  * second_order  0 (default) or 1: m1_bind_state also allocates the buffer
  *         of m1_step_rk2 (the first-stage state, 4 m + 4 fields), so that no
- *         step call allocates */
+ *         step call allocates
+ * limiter M1_LIMITER_PLM (default) or M1_LIMITER_LIMO3: phi(theta) of
+ *         theta = (far-side difference) / (face-side difference),
+ *         phi = max(0, min(p3, max(-theta/2, min(2 theta, p3, 3/2)))),
+ *         p3 = (2 + theta)/3, the face value u + phi (face-side divided
+ *         difference) (x_face - x_cell); each face of a cell has its own
+ *         slope.  The face treatment (recon) applies to either. */
 typedef struct {
     double c;
     double a_rad;
@@ -109,6 +119,7 @@ typedef struct {
     int riemann;
     int absorb_only;
     int second_order;
+    int limiter;
 } m1_params;
 
 /* Caller-owned device state bound to a context (see conventions). */

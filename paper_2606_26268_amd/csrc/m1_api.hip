@@ -198,7 +198,7 @@ static m1_status upload_metric(m1_ctx *c, const HostMetric &M)
         for (size_t t = 0; t < arrs[a]->size(); ++t) f[t] = float((*arrs[a])[t]);
     }
     for (int d = 0; d < 3; ++d) std::memcpy(&host[offv[d]], M.vol[d].data(), M.vol[d].size() * 8);
-    hipError_t e = hipMalloc(&c->metric_buf, pos);
+    hipError_t e = device_alloc(&c->metric_buf, pos);
     if (e != hipSuccess) return fail(M1_ENOMEM, "metric allocation failed");
     e = hipMemcpy(c->metric_buf, host.data(), pos, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "metric upload");
@@ -283,6 +283,7 @@ m1_status m1_params_default(double c_hat, m1_params *p)
     p->riemann = M1_RIEMANN_HLL;
     p->absorb_only = 0;
     p->second_order = 0;
+    p->limiter = M1_LIMITER_PLM;
     return M1_OK;
 }
 
@@ -329,6 +330,8 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
         return fail(M1_EINVAL, "m1_create: absorb_only must be 0 or 1");
     if (par.second_order != 0 && par.second_order != 1)
         return fail(M1_EINVAL, "m1_create: second_order must be 0 or 1");
+    if (par.limiter != M1_LIMITER_PLM && par.limiter != M1_LIMITER_LIMO3)
+        return fail(M1_EINVAL, "m1_create: unknown limiter");
     if (!(par.c > 0.0) || !(par.gamma > 1.0) || !(par.a_rad > 0.0))
         return fail(M1_EINVAL, "m1_create: c, a_rad must be > 0 and gamma > 1");
     m1_ctx *c = new (std::nothrow) m1_ctx();
@@ -396,14 +399,14 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
     // allocation succeeded: a failed rebind leaves the previous binding (its
     // buffers and fields) intact and usable
     void *nscr = nullptr, *nrk = nullptr;
-    hipError_t e = hipMalloc(&nscr, bytes);
+    hipError_t e = device_alloc(&nscr, bytes);
     if (e != hipSuccess) return fail(M1_ENOMEM, "m1_bind_state: scratch allocation failed");
     size_t rad = 0;
     if (c->par.second_order) {
         // the first-stage state of m1_step_rk2: the four radiation fields of
         // all groups (group-major, as the bound arrays), then mx, my, mz, E_g
         rad = ((size_t(G) * N * es + 255) / 256) * 256;
-        e = hipMalloc(&nrk, 4 * rad + 4 * N * sizeof(double));
+        e = device_alloc(&nrk, 4 * rad + 4 * N * sizeof(double));
         if (e != hipSuccess) {
             hipFree(nscr);
             return fail(M1_ENOMEM, "m1_bind_state: second-order buffer allocation failed");
@@ -479,7 +482,7 @@ m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1
     // the new table is uploaded before the old one is released: on failure
     // the context keeps its previous opacity source unchanged
     float *tab = nullptr;
-    hipError_t e = hipMalloc(&tab, 2 * n * sizeof(float));
+    hipError_t e = device_alloc(reinterpret_cast<void **>(&tab), 2 * n * sizeof(float));
     if (e != hipSuccess) return fail(M1_ENOMEM, "m1_set_opacity_table: allocation failed");
     e = hipMemcpy(tab, kP, n * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(tab + n, kR, n * sizeof(float), hipMemcpyHostToDevice);

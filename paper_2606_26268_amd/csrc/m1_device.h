@@ -1,7 +1,8 @@
 // m1_device.h -- device-side building blocks of the M1 step for gfx950:
 // Levermore closure with the Sect. 2.6 signal speeds and the physical flux
 // of one state, the HLL interface flux with the optical-depth limiter, the
-// van Leer slope and the f-preserving face fix (Eq. f_reconstruct).
+// van Leer and LimO3 slopes and the f-preserving face fix
+// (Eq. f_reconstruct).
 // Templated on the working precision R (double or float).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -399,6 +400,40 @@ __device__ __forceinline__ void slopes4(const R qm[4], const R q0[4], const R qp
 {
 #pragma unroll
     for (int v = 0; v < 4; ++v) s[v] = vanleer_fast((q0[v] - qm[v]) * wl, (qp[v] - q0[v]) * wr);
+}
+
+// LimO3 limited slope (Cada and Torrilhon 2009, the compact third-order
+// reconstruction Sect. 2.5 names) of a cell for its face on the side of the
+// divided difference dnear, dfar being the one on the other side:
+// phi(theta) dnear with theta = dfar / dnear and
+//   phi = max(0, min(p3, max(-theta/2, min(2 theta, p3, 3/2)))),
+//   p3 = (2 + theta) / 3 (the unlimited third-order reconstruction).
+// Evaluated without a division: with s = sign(dnear), a = s dfar and
+// b = |dnear|, phi dnear = s b phi, and b >= 0 scales through every min and
+// max, so phi dnear = s max(0, min(q, max(-a/2, min(2a, q, 3b/2)))) with
+// q = (2b + a) / 3; dnear = 0 gives 0 (the limit of phi dnear).
+template <typename R>
+__device__ __forceinline__ R limo3(R dfar, R dnear)
+{
+    const R s = dnear < R(0) ? R(-1) : R(1);
+    const R a = s * dfar, b = s * dnear;
+    const R q = (R(2) * b + a) * R(1.0 / 3.0);
+    const R inner = vmin(vmin(R(2) * a, q), R(1.5) * b);
+    return s * vmax(R(0), vmin(q, vmax(R(-0.5) * a, inner)));
+}
+
+// LimO3 slopes of the four fields of cell m from cells m-1, m, m+1: lo for
+// the lower face (near side m-1), hi for the upper face (near side m+1).
+template <typename R>
+__device__ __forceinline__ void limo3_slopes4(const R qm[4], const R q0[4], const R qp[4], R wl, R wr, R lo[4],
+                                              R hi[4])
+{
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const R dl = (q0[v] - qm[v]) * wl, dr = (qp[v] - q0[v]) * wr;
+        hi[v] = limo3(dl, dr);
+        lo[v] = limo3(dr, dl);
+    }
 }
 
 } // namespace m1

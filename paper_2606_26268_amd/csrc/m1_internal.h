@@ -151,6 +151,20 @@ struct m1_ctx {
 };
 
 namespace m1 {
+// Device allocation that leaves no error behind: a failed hipMalloc also
+// sets the thread's last HIP error, which the next launch check (the
+// library's or the caller's, e.g. torch's) would report as its own; it is
+// read back and cleared here, the failure being returned instead.
+inline hipError_t device_alloc(void **p, size_t bytes)
+{
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+    }
+    return e;
+}
+
 // kernel launchers (defined in the .hip translation units)
 hipError_t launch_transport(m1_ctx *c, double dt);
 hipError_t launch_implicit(m1_ctx *c, double dt);

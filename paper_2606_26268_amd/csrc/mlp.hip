@@ -104,7 +104,7 @@ int mlp_pack(m1_ctx *c, const float *theta, const double *norm)
     std::vector<float> pk;
     host_pack(theta, norm, pk);
     if (!c->mlp_dev) {
-        if (hipMalloc(&c->mlp_dev, MLP_TRAIN_PACK * sizeof(float)) != hipSuccess) {
+        if (device_alloc(reinterpret_cast<void **>(&c->mlp_dev), MLP_TRAIN_PACK * sizeof(float)) != hipSuccess) {
             set_error("MLP buffer allocation failed");
             return -2;
         }
@@ -565,7 +565,7 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
     const long n_eval_blocks = (cfg->n_eval + 255) / 256;
     float *buf = nullptr;
     const size_t nbuf = 3 * size_t(NP) + size_t(nblk) * NP + nblk + cfg->steps + 2 * n_eval_blocks;
-    if (hipMalloc(&buf, nbuf * sizeof(float)) != hipSuccess) {
+    if (device_alloc(reinterpret_cast<void **>(&buf), nbuf * sizeof(float)) != hipSuccess) {
         set_error("m1_mlp_train: allocation failed");
         return int(M1_ENOMEM);
     }
@@ -657,7 +657,7 @@ int mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, fl
     const int nblk = int(n / 64);
     float *buf = nullptr;
     const size_t nbuf = size_t(nblk) * NP + nblk + NP + 1;
-    if (hipMalloc(&buf, nbuf * sizeof(float)) != hipSuccess) {
+    if (device_alloc(reinterpret_cast<void **>(&buf), nbuf * sizeof(float)) != hipSuccess) {
         set_error("m1_mlp_gradient: allocation failed");
         return int(M1_ENOMEM);
     }

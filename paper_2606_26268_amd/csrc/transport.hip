@@ -24,6 +24,7 @@ struct TArgs {
     Metric<R> m;
     R dt, c_hat, e_floor;
     int recon, riemann;
+    int limo3;                 // LimO3 slopes instead of PLM van Leer
     int special;               // some side is reflective or fixed
     R bcs[3][2][4];            // ghost state of fixed sides
     long gs_in, gs_out, gs_tau; // element strides between frequency groups
@@ -137,11 +138,20 @@ __device__ __forceinline__ void direction_div(const TArgs<R> &a, int base, int s
         const R dB = (q[2][v] - q[1][v]) * winv[t + 2];
         const R dC = (q[3][v] - q[2][v]) * winv[t + 3];
         const R dD = (q[4][v] - q[3][v]) * winv[t + 4];
-        const R sm = vanleer(dA, dB), s0 = vanleer(dB, dC), sp = vanleer(dC, dD);
-        Lm[v] = q[1][v] + sm * hp[t + 1];
-        Rt[v] = q[2][v] - s0 * hm[t + 2];
-        Lt[v] = q[2][v] + s0 * hp[t + 2];
-        Rp[v] = q[3][v] - sp * hm[t + 3];
+        if (a.limo3) {
+            // each face takes its own slope: the difference on the face side
+            // is the near one
+            Lm[v] = q[1][v] + limo3(dA, dB) * hp[t + 1];
+            Rt[v] = q[2][v] - limo3(dC, dB) * hm[t + 2];
+            Lt[v] = q[2][v] + limo3(dB, dC) * hp[t + 2];
+            Rp[v] = q[3][v] - limo3(dD, dC) * hm[t + 3];
+        } else {
+            const R sm = vanleer(dA, dB), s0 = vanleer(dB, dC), sp = vanleer(dC, dD);
+            Lm[v] = q[1][v] + sm * hp[t + 1];
+            Rt[v] = q[2][v] - s0 * hm[t + 2];
+            Lt[v] = q[2][v] + s0 * hp[t + 2];
+            Rp[v] = q[3][v] - sp * hm[t + 3];
+        }
     }
     if (a.recon == M1_RECON_FPRESERVE) {
         ffix(Lm, q[1]);
@@ -306,8 +316,12 @@ __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
 // waves per SIMD (the second argument of the bound), i.e. at most 128 and
 // 168 VGPRs: the general one just exceeds its bound otherwise, the default
 // one fits exactly.
-template <typename R, int GEOM, bool GENERAL, int TYB>
-__global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 3 : 4) : 1))
+// LIMO3 (general kernel only): each donor cell keeps two slopes per
+// direction, one for its lower and one for its upper face; the extra
+// registers need a bound of two waves per SIMD in FP32 (three spilled) and
+// the 32 x 8 tile in FP64 (the 512-thread block spilled).
+template <typename R, int GEOM, bool GENERAL, int TYB, bool LIMO3 = false>
+__global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? (LIMO3 ? 2 : 3) : 4) : 1))
     k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
 {
     using T = Tile<TYB>;
@@ -321,7 +335,9 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
     __shared__ R sq[4][HY][HX];
     __shared__ R st[HY][HX];
     __shared__ R scf[2][HY][HX];        // |F|^2 and 1 / E of the staged cells
-    __shared__ R ss[4][NXS + NYS];      // slopes: x tasks, then y tasks
+    static_assert(GENERAL || !LIMO3, "LimO3 only in the general kernel");
+    __shared__ R ss[4][NXS + NYS];      // slopes: x tasks, then y tasks (LimO3: upper-face slopes)
+    __shared__ R ssl[LIMO3 ? 4 : 1][LIMO3 ? NXS + NYS : 1];   // LimO3: lower-face slopes
     __shared__ R sfx[4][TY][TX + 1];
     __shared__ R sfy[4][TY + 1][TX];
     R *const sqf = &sq[0][0][0];
@@ -474,11 +490,22 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
         const R Tm = a.tau[zlin(z0 - 1, col)];
         T1 = a.tau[zlin(z0, col)];
         T2 = a.tau[zlin(z0 + 1, col)];
-        slopes4(Q0, W[0], W[1], wz[z0 + 1], wz[z0 + 2], Szm);
-        slopes4(W[0], W[1], W[2], wz[z0 + 2], wz[z0 + 3], Sz0);
         C1 = centre_of(W[1]);
-        face_flux_s<R>(2, W[0], W[1], Szm, Sz0, centre_of(W[0]), C1, hpz[z0 + 1], hmz[z0 + 2], Tm, T1, a.c_hat,
-                       Fzlo, recon, riemann);
+        if constexpr (LIMO3) {
+            // the face below plane z0 takes the upper-face slope of plane
+            // z0 - 1 and the lower-face slope of plane z0; Sz0 carries the
+            // upper-face slope of the current plane
+            R lo_m[4], lo_0[4];
+            limo3_slopes4(Q0, W[0], W[1], wz[z0 + 1], wz[z0 + 2], lo_m, Szm);
+            limo3_slopes4(W[0], W[1], W[2], wz[z0 + 2], wz[z0 + 3], lo_0, Sz0);
+            face_flux_s<R>(2, W[0], W[1], Szm, lo_0, centre_of(W[0]), C1, hpz[z0 + 1], hmz[z0 + 2], Tm, T1,
+                           a.c_hat, Fzlo, recon, riemann);
+        } else {
+            slopes4(Q0, W[0], W[1], wz[z0 + 1], wz[z0 + 2], Szm);
+            slopes4(W[0], W[1], W[2], wz[z0 + 2], wz[z0 + 3], Sz0);
+            face_flux_s<R>(2, W[0], W[1], Szm, Sz0, centre_of(W[0]), C1, hpz[z0 + 1], hmz[z0 + 2], Tm, T1,
+                           a.c_hat, Fzlo, recon, riemann);
+        }
     }
 
     for (int k = z0; k < z1; ++k) {
@@ -520,13 +547,24 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
                 q0[v] = sqf[v * QS + s_ctr[p]];
                 qp[v] = sqf[v * QS + s_ctr[p] + str];
             }
-            slopes4(qm, q0, qp, s_wl[p], s_wr[p], sl);
+            if constexpr (LIMO3) {
+                R lo[4];
+                limo3_slopes4(qm, q0, qp, s_wl[p], s_wr[p], lo, sl);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ssl[v][s_slot[p]] = lo[v];
+            } else {
+                slopes4(qm, q0, qp, s_wl[p], s_wr[p], sl);
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) ss[v][s_slot[p]] = sl[v];
         }
-        // z slope of plane k+1
-        R Sz1[4];
-        slopes4(W[1], W[2], W[3], wz[k + 3], wz[k + 4], Sz1);
+        // z slope(s) of plane k+1 (LimO3: Sz1 its upper-face slope, Sz1l
+        // its lower-face one)
+        R Sz1[4], Sz1l[4];
+        if constexpr (LIMO3)
+            limo3_slopes4(W[1], W[2], W[3], wz[k + 3], wz[k + 4], Sz1l, Sz1);
+        else
+            slopes4(W[1], W[2], W[3], wz[k + 3], wz[k + 4], Sz1);
         __syncthreads();
 
         // x faces (left face of column f) and y faces (lower face of row g)
@@ -541,7 +579,7 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
                 qb[v] = sqf[v * QS + b];
                 qc[v] = sqf[v * QS + b + qst];
                 slb[v] = ss[v][sb];
-                slc[v] = ss[v][sb + sst];
+                slc[v] = LIMO3 ? ssl[v][sb + sst] : ss[v][sb + sst];
             }
             face_flux_s<R>(d, qb, qc, slb, slc, Centre<R>{scf2[b], scie[b]}, Centre<R>{scf2[b + qst], scie[b + qst]},
                            f_hp[p], f_hm[p], stf[b], stf[b + qst], a.c_hat, fl, recon, riemann);
@@ -552,8 +590,8 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
         }
         // z face above the plane from the register window
         const Centre<R> C2 = centre_of(W[2]);
-        face_flux_s<R>(2, W[1], W[2], Sz0, Sz1, C1, C2, hpz[k + 2], hmz[k + 3], T1, T2, a.c_hat, Fzhi, recon,
-                       riemann);
+        face_flux_s<R>(2, W[1], W[2], Sz0, LIMO3 ? Sz1l : Sz1, C1, C2, hpz[k + 2], hmz[k + 3], T1, T2, a.c_hat,
+                       Fzhi, recon, riemann);
         __syncthreads();
 
         if (live) {
@@ -618,13 +656,14 @@ static int resident_blocks(const void *kern, int block)
 // Launch with tile height TYB; with max_rounds > 0, only if the launch then
 // takes at most that many rounds of resident blocks (returns whether it
 // launched).
-template <typename R, int GEOM, bool GENERAL, int TYB>
+template <typename R, int GEOM, bool GENERAL, int TYB, bool LIMO3 = false>
 static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, long max_rounds)
 {
     using T = Tile<TYB>;
     constexpr int TX = T::TX, TY = T::TY, NT = T::NT;
     const int tiles_x = (c->n[0] + TX - 1) / TX, tiles_y = (c->n[1] + TY - 1) / TY;
-    const long slots = resident_blocks(reinterpret_cast<const void *>(&k_transport3d<R, GEOM, GENERAL, TYB>), NT);
+    const long slots =
+        resident_blocks(reinterpret_cast<const void *>(&k_transport3d<R, GEOM, GENERAL, TYB, LIMO3>), NT);
     int nz = 8;
     double best = 1e300;
     long rounds = 1;
@@ -641,7 +680,7 @@ static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, long max_ro
     if (max_rounds > 0 && rounds > max_rounds) return false;
     const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
     const int launched = ((nblocks + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_transport3d<R, GEOM, GENERAL, TYB>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz,
+    hipLaunchKernelGGL((k_transport3d<R, GEOM, GENERAL, TYB, LIMO3>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz,
                        tiles_x, tiles_y, nblocks);
     return true;
 }
@@ -650,13 +689,13 @@ static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, long max_ro
 // blocks (the 192x96x192 and 128^3 grids: 1.5-3 % faster transport than
 // 32 x 8), else 32 x 8 (on the 256^3 grid and eight groups at 128^3,
 // launches of four to sixteen rounds, the taller blocks were 2-4 % slower).
-template <typename R, int GEOM, bool GENERAL>
+template <typename R, int GEOM, bool GENERAL, bool LIMO3 = false>
 static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
 {
-    if constexpr (!(sizeof(R) == 4 && GENERAL)) {
-        if (launch_tile<R, GEOM, GENERAL, 16>(c, a, ngrp, 2)) return;
+    if constexpr (!(sizeof(R) == 4 && GENERAL) && !LIMO3) {
+        if (launch_tile<R, GEOM, GENERAL, 16, LIMO3>(c, a, ngrp, 2)) return;
     }
-    launch_tile<R, GEOM, GENERAL, 8>(c, a, ngrp, 0);
+    launch_tile<R, GEOM, GENERAL, 8, LIMO3>(c, a, ngrp, 0);
 }
 
 // One transport launch for every frequency group (grid y = group; one group
@@ -688,6 +727,7 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met, const voi
     a.e_floor = R(c->par.e_floor);
     a.recon = c->par.recon;
     a.riemann = c->par.riemann;
+    a.limo3 = c->par.limiter == M1_LIMITER_LIMO3;
     a.special = 0;
     for (int d = 0; d < 3; ++d)
         for (int sd = 0; sd < 2; ++sd) {
@@ -697,18 +737,17 @@ static hipError_t launch_t(m1_ctx *c, double dt, const Metric<R> &met, const voi
     a.cnt = c->cnt;
     if (c->ndim == 3) {
         const bool var = c->par.recon != M1_RECON_FPRESERVE || c->par.riemann != M1_RIEMANN_HLL || a.special;
-#define M1_T3D(GM, V) launch_tiled<R, GM, V>(c, a, ngrp)
+#define M1_T3D(GM, V, L) launch_tiled<R, GM, V, L>(c, a, ngrp)
+#define M1_T3D_ANY(GM)                  \
+    if (a.limo3) M1_T3D(GM, true, true);  \
+    else if (var) M1_T3D(GM, true, false); \
+    else M1_T3D(GM, false, false)
         switch (c->geom) {
-        case M1_CARTESIAN:
-            if (var) M1_T3D(M1_CARTESIAN, true); else M1_T3D(M1_CARTESIAN, false);
-            break;
-        case M1_CYLINDRICAL:
-            if (var) M1_T3D(M1_CYLINDRICAL, true); else M1_T3D(M1_CYLINDRICAL, false);
-            break;
-        default:
-            if (var) M1_T3D(M1_SPHERICAL, true); else M1_T3D(M1_SPHERICAL, false);
-            break;
+        case M1_CARTESIAN: M1_T3D_ANY(M1_CARTESIAN); break;
+        case M1_CYLINDRICAL: M1_T3D_ANY(M1_CYLINDRICAL); break;
+        default: M1_T3D_ANY(M1_SPHERICAL); break;
         }
+#undef M1_T3D_ANY
 #undef M1_T3D
         return hipGetLastError();
     }

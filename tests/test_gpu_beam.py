@@ -1,0 +1,51 @@
+"""The free-streaming beam of Sect. 3.2 on the GPU at the paper's 300 x 300
+resolution, Courant number 0.4, HLL, f-preserving face fix, second-order
+steps, FP64 and FP32 forms, PLM and LimO3: the emitter reading and the cuts
+are those of beam_common.  The peak and width changes between the cuts at
+x = 1 and x = 4.35 are printed for each form; LimO3 must land in the band
+around the printed -8 % / +7 % (as the oracle does), and the two precisions
+must agree on both changes to 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_26268_amd import inputs as I
+from tests import beam_common as B
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(limiter, precision):
+    from paper_2606_26268_amd import m1
+    N = B.PAPER["resolution"]
+    p = I.make_beam(N=N)
+    p.limiter = limiter
+    s = m1.Solver(p, precision, second_order=True)
+    m = torch.from_numpy(B.emitter_mask(N)).to(s.device)
+    Eb, Fxb, Fyb = B.emitter_state()
+    for _ in range(int(B.T_END / p.dt)):
+        s.step(p.dt, 1, rk2=True)
+        s.sync()
+        for k, v in (("E", Eb), ("Fx", Fxb), ("Fy", Fyb)):
+            s.t[k][0][m] = v
+        torch.cuda.synchronize()
+    E = s.t["E"][0].to(torch.float64).cpu().numpy()
+    s.close()
+    return E
+
+
+@pytest.mark.parametrize("limiter", [0, 1], ids=["plm", "limo3"])
+def test_beam_peak_and_width(limiter):
+    res = {}
+    for precision in ("p64", "f32"):
+        dp, dw, dy = B.changes(_run(limiter, precision))
+        res[precision] = (dp, dw)
+        say(f"  beam {['PLM', 'LimO3'][limiter]} {precision}: peak {100 * dp:+.2f} %, FWHM {100 * dw:+.2f} %, "
+            f"centre shift {dy:.3f} (paper: -8 %, +7 %)")
+        assert abs(dy - (B.CUTS[1] - B.CUTS[0])) < 5.0 / 300
+    assert np.allclose(res["p64"], res["f32"], atol=1e-3), res
+    if limiter == 1:
+        dp, dw = res["p64"]
+        assert B.PEAK_BAND[0] < dp < B.PEAK_BAND[1], dp
+        assert B.FWHM_BAND[0] < dw < B.FWHM_BAND[1], dw

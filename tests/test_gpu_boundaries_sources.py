@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2606_26268_amd import inputs as I
-from tests.gpu_common import TOL_P64, assert_close, assert_close_f32, rel_errors, run_gpu, run_oracle, say
+from tests.gpu_common import TOL_P64, assert_close, assert_close_f32, fp32_response, rel_errors, run_gpu, run_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_boundary_parity(orc, name, precision):
     if precision == "p64":
         assert_close(got, ref, TOL_P64, label=name)
     else:
-        assert_close_f32(got, ref, label=name)
+        assert_close_f32(got, ref, fp32_response(orc, p, 12), label=name)
 
 
 def test_spherical_reflective_equator(orc):
@@ -84,7 +84,7 @@ def test_irradiation_and_absorption_parity(orc, precision, absorb):
         assert_close(got, ref, TOL_P64, label=f"irr/abs{absorb}")
     else:
         # c / c_hat = 10 amplifies the FP32 rounding of E in E_g
-        assert_close_f32(got, ref, label=f"irr/abs{absorb}", gas_scale=10.0)
+        assert_close_f32(got, ref, fp32_response(orc, p, 8), label=f"irr/abs{absorb}", gas_scale=10.0)
 
 
 def _sensitivity(orc, p, steps, eps, ref, fields):
@@ -126,14 +126,27 @@ def test_shadow_parity(orc, precision):
         return
     # FP32: E and E_g per field; the flux as one vector field (F_y is only
     # ~2e-4 of F_x here, made at the beam edges, so its own relative error
-    # says little), each against the rel-L1 1e-5 target
-    dF = np.sqrt(sum((got[k] - ref[k]) ** 2 for k in ("Fx", "Fy", "Fz")))
-    Fn = np.sqrt(sum(ref[k] ** 2 for k in ("Fx", "Fy", "Fz")))
-    vec = (dF.sum() / Fn.sum(), dF.max() / Fn.max())
-    say("  shadow f32: " + " ".join(f"{k}:{errs[k][0]:.1e}/{errs[k][1]:.1e}" for k in fields) +
-        f" |F|:{vec[0]:.1e}/{vec[1]:.1e}")
-    for k, (l1, linf) in (("E", errs["E"]), ("Eg", errs["Eg"]), ("F", vec)):
-        assert l1 <= 1e-5 and linf <= 1e-2, (k, l1, linf)
+    # says little), each within the bounds the oracle's responses to the
+    # FP32 disturbances give (rel-L1 and rel-Linf, as assert_close_f32)
+    resp = fp32_response(orc, p, steps)
+
+    def vec(a):
+        dF = np.sqrt(sum((a[k] - ref[k]) ** 2 for k in ("Fx", "Fy", "Fz")))
+        Fn = np.sqrt(sum(ref[k] ** 2 for k in ("Fx", "Fy", "Fz")))
+        return dF.sum() / Fn.sum(), dF.max() / Fn.max()
+
+    got_e = {"E": errs["E"], "Eg": errs["Eg"], "F": vec(got)}
+    res = {}
+    for name in ("fp32", "flip"):
+        r = rel_errors(resp[name], ref, fields)
+        res[name] = {"E": r["E"], "Eg": r["Eg"], "F": vec(resp[name])}
+    say("  shadow f32 (oracle fp32 / flip responses): " +
+        " ".join(f"{k}:{v[0]:.1e}/{v[1]:.1e} ({res['fp32'][k][0]:.1e}/{res['fp32'][k][1]:.1e}, "
+                 f"{res['flip'][k][0]:.1e}/{res['flip'][k][1]:.1e})" for k, v in got_e.items()))
+    for k, (l1, linf) in got_e.items():
+        small, big = res["fp32"][k], res["flip"][k]
+        assert l1 <= max(1e-5, 4 * small[0]), (k, l1, small)
+        assert linf <= max(1e-5, 4 * small[1], big[1]), (k, linf, small, big)
 
 
 def test_boundary_errors():

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2606_26268_amd import inputs as I
-from tests.gpu_common import TOL_P64, TOL_P64_F1, assert_close, assert_close_f32, say
+from tests.gpu_common import TOL_P64, TOL_P64_F1, assert_close, assert_close_f32, fp32_response, say
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,8 @@ def test_c4_full_size_steps(orc):
     got = s.state()
     s.close()
     ref, _ = orc.Oracle(p, dict(theta=theta.astype(np.float64), norm=norm, bf16=True)).run(p.fields, p.dt, 3)
-    assert_close_f32(got, ref, label="c4 full")
+    assert_close_f32(got, ref, fp32_response(orc, p, 3, mlp=dict(theta=theta.astype(np.float64), norm=norm, bf16=True)),
+                     label="c4 full")
 
 
 @pytest.mark.parametrize("precision", ["p64", "f32"])
@@ -67,7 +68,7 @@ def test_multigroup_full_size_steps(orc, precision):
         say(f"  oracle f-clips after transport / implicit: {cnt[1]} / {cnt[2]}")
         assert_close(got, ref, tol, fields=MG_FIELDS, label="mg8 full p64")
     else:
-        assert_close_f32(got, ref, fields=MG_FIELDS, label="mg8 full f32")
+        assert_close_f32(got, ref, fp32_response(orc, p, 3), fields=MG_FIELDS, label="mg8 full f32")
 
 
 @pytest.mark.parametrize("precision", ["p64", "f32"])
@@ -85,7 +86,7 @@ def test_multigroup_rk2_full_size_step(orc, precision):
         tol = TOL_P64 if cnt[1] + cnt[2] == 0 else TOL_P64_F1
         assert_close(got, ref, tol, fields=MG_FIELDS, label="mg8 rk2 full p64")
     else:
-        assert_close_f32(got, ref, fields=MG_FIELDS, label="mg8 rk2 full f32")
+        assert_close_f32(got, ref, fp32_response(orc, p, 1, rk2=True), fields=MG_FIELDS, label="mg8 rk2 full f32")
 
 
 @pytest.mark.parametrize("precision", ["p64", "f32"])
@@ -103,7 +104,7 @@ def test_rk2_full_size_steps(orc, precision):
     if precision == "p64":
         assert_close(got, ref, TOL_P64, label="rk2 full p64")
     else:
-        assert_close_f32(got, ref, label="rk2 full f32")
+        assert_close_f32(got, ref, fp32_response(orc, p, 2, rk2=True), label="rk2 full f32")
 
 
 @pytest.mark.parametrize("precision", ["p64", "f32"])
@@ -129,7 +130,7 @@ def test_general_kernel_full_size_steps(orc, precision):
         assert_close(got, ref, TOL_P64_F1, label="general full p64")
         assert diag["counters"][:3] == list(cnt[:3])
     else:
-        assert_close_f32(got, ref, label="general full f32")
+        assert_close_f32(got, ref, fp32_response(orc, p, 5), label="general full f32")
 
 
 @pytest.mark.parametrize("precision", ["p64", "f32"])
@@ -161,7 +162,7 @@ def test_pulse_full_size_rk2_steps(orc, precision):
         assert np.abs(E - np.flip(E, 0)).max() <= 1e-12 * E.max()
         assert np.abs(E - E.transpose(2, 1, 0)).max() <= 1e-12 * E.max()
     else:
-        assert_close_f32(got, ref, fields=rad, label="pulse full f32")
+        assert_close_f32(got, ref, fp32_response(orc, p, 2, rk2=True), fields=rad, label="pulse full f32")
     for c in ("x", "y", "z"):
         d = np.abs(got["m" + c] - ref["m" + c])
         fs = np.abs(ref["F" + c]) / p.c_hat
