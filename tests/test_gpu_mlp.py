@@ -53,6 +53,12 @@ def test_inference_matches_oracle(orc):
     dP = np.abs(np.log10(kP.cpu().numpy()) - np.log10(rP))
     dR = np.abs(np.log10(kR.cpu().numpy()) - np.log10(rR))
     say(f"  mlp inference max |dlog10 k|: P {dP.max():.2e} R {dR.max():.2e}")
+    # both against the exact network (FP64 throughout), for the record
+    oe = orc.Oracle(p, dict(theta=th.astype(np.float64), norm=norm, bf16=False))
+    eP, eR = oe.opacity(rho, T)
+    say(f"  against the exact network: GPU P {np.abs(np.log10(kP.cpu().numpy()) - np.log10(eP)).max():.2e} "
+        f"R {np.abs(np.log10(kR.cpu().numpy()) - np.log10(eR)).max():.2e}; oracle's emulation "
+        f"P {np.abs(np.log10(rP) - np.log10(eP)).max():.2e} R {np.abs(np.log10(rR) - np.log10(eR)).max():.2e}")
     assert dP.max() < 2e-5 and dR.max() < 2e-5
     s.close()
 
