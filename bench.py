@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=None, help="override the Adam step count")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="only time the CPU oracle on bounded samples of the FP64 workloads (no GPU)")
     return ap.parse_args()
 
 
@@ -69,7 +71,12 @@ def train_surrogate(m1, I, torch, solver, steps):
     return rep
 
 
-REPS = 5
+# timed repetitions of the K steps; the median is reported and every
+# repetition listed.  After an idle GPU the clock ramps up over the first
+# ~100 steps of this workload (20-step repetitions after a 5-step warm-up
+# measured 0.310, 0.282, 0.270, 0.264, 0.256 ms/step), so with short
+# warm-ups the median of eleven repetitions is the sustained rate
+REPS = 11
 
 
 def time_form(m1, torch, prob, precision, K, W, mlp_train_steps=0, I=None, rk2=False, reps=REPS):
@@ -280,6 +287,31 @@ def oracle_baseline(I, weights=None, seconds_target=15.0, threads=None, shape=(9
                 sample=f"spherical recipe with the MLP opacity on {shp} cells, {steps} steps, {t:.1f} s")
 
 
+def oracle_configs(I):
+    """The FP64 oracle on the host cores, timed per step on bounded samples
+    of the FP64 workloads (whole steps of the full grids with all threads;
+    one thread on a 64^3 box of the turbulent-box recipe): one JSON line."""
+    from oracle import oracle as orc
+    runs = [("c1 128^3 turbulent box, constant opacity", lambda: I.make_c1(), None, 2),
+            ("c1 recipe on 64^3 cells, one thread", lambda: I.make_turbulent_box(64, 1, 1.0417e-4, 1, "c1s"), 1, 1),
+            ("c3 spherical 192x96x192, bilinear table", lambda: I.make_c3(), None, 1),
+            ("c2 256^3 turbulent box, constant opacity", lambda: I.make_c2(), None, 1)]
+    allt = orc.max_threads()
+    out = {"cpu_model": cpu_model(), "runs": []}
+    for label, mk, threads, steps in runs:
+        p = mk()
+        orc.set_threads(threads if threads else allt)
+        o = orc.Oracle(p)
+        t0 = time.perf_counter()
+        o.run(p.fields, p.dt, steps)
+        t = time.perf_counter() - t0
+        out["runs"].append(dict(workload=label, cores=orc.max_threads(), steps=steps, seconds=round(t, 2),
+                                cell_updates_per_s=p.ncells * steps / t))
+        log(f"  {label}: {p.ncells * steps / t:.3e} cell updates/s")
+    orc.set_threads(allt)
+    print(json.dumps(out))
+
+
 def _log10_opacity(m1, torch, ctx, rho, T):
     """log10 kappa_P, log10 kappa_R of a context's opacity source at host
     (rho, T) points, evaluated on the device."""
@@ -407,6 +439,10 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.oracle_configs:
+        from paper_2606_26268_amd import inputs as I
+        oracle_configs(I)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1"}))
