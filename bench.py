@@ -287,27 +287,31 @@ def oracle_baseline(I, weights=None, seconds_target=15.0, threads=None, shape=(9
                 sample=f"spherical recipe with the MLP opacity on {shp} cells, {steps} steps, {t:.1f} s")
 
 
-def oracle_configs(I):
-    """The FP64 oracle on the host cores, timed per step on bounded samples
-    of the FP64 workloads (whole steps of the full grids with all threads;
-    one thread on a 64^3 box of the turbulent-box recipe): one JSON line."""
+def oracle_configs(I, seconds_target=8.0):
+    """The FP64 oracle on the host cores, on the FP64 workloads at full grid
+    size: whole steps, one at a time, until seconds_target has passed or
+    the workload's own step count is reached; with all host threads, and
+    the 128^3 box also with one thread.  Prints one JSON line."""
     from oracle import oracle as orc
-    runs = [("c1 128^3 turbulent box, constant opacity", lambda: I.make_c1(), None, 2),
-            ("c1 recipe on 64^3 cells, one thread", lambda: I.make_turbulent_box(64, 1, 1.0417e-4, 1, "c1s"), 1, 1),
-            ("c3 spherical 192x96x192, bilinear table", lambda: I.make_c3(), None, 1),
-            ("c2 256^3 turbulent box, constant opacity", lambda: I.make_c2(), None, 1)]
+    runs = [("c1 128^3 turbulent box, constant opacity", I.make_c1, None),
+            ("c1 128^3 turbulent box, constant opacity", I.make_c1, 1),
+            ("c3 spherical 192x96x192, bilinear table", I.make_c3, None),
+            ("c2 256^3 turbulent box, constant opacity", I.make_c2, None)]
     allt = orc.max_threads()
     out = {"cpu_model": cpu_model(), "runs": []}
-    for label, mk, threads, steps in runs:
+    for label, mk, threads in runs:
         p = mk()
         orc.set_threads(threads if threads else allt)
         o = orc.Oracle(p)
-        t0 = time.perf_counter()
-        o.run(p.fields, p.dt, steps)
-        t = time.perf_counter() - t0
+        st, steps, t = p.fields, 0, 0.0
+        while t < seconds_target and steps < p.steps:
+            t0 = time.perf_counter()
+            st, _ = o.run(st, p.dt, 1)
+            t += time.perf_counter() - t0
+            steps += 1
         out["runs"].append(dict(workload=label, cores=orc.max_threads(), steps=steps, seconds=round(t, 2),
                                 cell_updates_per_s=p.ncells * steps / t))
-        log(f"  {label}: {p.ncells * steps / t:.3e} cell updates/s")
+        log(f"  {label}, {orc.max_threads()} threads: {p.ncells * steps / t:.3e} cell updates/s")
     orc.set_threads(allt)
     print(json.dumps(out))
 
