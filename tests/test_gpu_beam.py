@@ -4,7 +4,12 @@ steps, FP64 and FP32 forms, PLM and LimO3: the emitter reading and the cuts
 are those of beam_common.  The peak and width changes between the cuts at
 x = 1 and x = 4.35 are printed for each form; LimO3 must land in the band
 around the printed -8 % / +7 % (as the oracle does), and the two precisions
-must agree on both changes to 1e-3."""
+must agree on both changes to 1e-3.
+
+At 1000 x 1000 with LimO3 (the resolution of the paper's comparison of
+face treatments, Sect. 3.2) the simple clip lets the beam explode, while
+the f-preserving fix and the PLUTO flat fallback keep it collimated, the
+latter with an undershoot of E beside the beam."""
 import numpy as np
 import pytest
 import torch
@@ -16,11 +21,11 @@ from tests.gpu_common import say
 pytestmark = pytest.mark.gpu
 
 
-def _run(limiter, precision):
+def _run(limiter, precision, N=None, recon=0):
     from paper_2606_26268_amd import m1
-    N = B.PAPER["resolution"]
+    N = B.PAPER["resolution"] if N is None else N
     p = I.make_beam(N=N)
-    p.limiter = limiter
+    p.limiter, p.recon = limiter, recon
     s = m1.Solver(p, precision, second_order=True)
     m = torch.from_numpy(B.emitter_mask(N)).to(s.device)
     Eb, Fxb, Fyb = B.emitter_state()
@@ -49,3 +54,23 @@ def test_beam_peak_and_width(limiter):
         dp, dw = res["p64"]
         assert B.PEAK_BAND[0] < dp < B.PEAK_BAND[1], dp
         assert B.FWHM_BAND[0] < dw < B.FWHM_BAND[1], dw
+
+
+def test_face_treatments_at_1000():
+    N, bg = 1000, B.PAPER["background_E"]
+    c = (np.arange(N) + 0.5) * B.PAPER["box"] / N
+    Y, X = np.meshgrid(c, c, indexing="ij")
+    x0, y0 = np.mean(B.PAPER["beam_x"]), np.mean(B.PAPER["beam_y"])
+    far = np.abs((Y - y0) - (X - x0)) / np.sqrt(2.0) > 0.25     # a quarter of a length unit off the axis
+    res = {}
+    for recon, name in ((0, "f-preserving"), (1, "PLUTO"), (2, "clip")):
+        E = _run(1, "p64", N=N, recon=recon)
+        e = E - bg
+        dp, dw, _ = B.changes(E)
+        res[name] = dict(far=float(e[far].sum() / e.sum()), min_rel=float(E.min() / bg), peak=dp)
+        say(f"  beam 1000^2 LimO3 {name}: energy a quarter unit off the axis {res[name]['far']:.2e}, "
+            f"min E / background {res[name]['min_rel']:.3f}, peak change {100 * dp:+.2f} %, FWHM {100 * dw:+.2f} %")
+    assert res["clip"]["far"] > 0.1 and res["clip"]["peak"] < -0.5          # explodes
+    for name in ("f-preserving", "PLUTO"):
+        assert abs(res[name]["far"]) < 1e-4 and abs(res[name]["peak"]) < 0.01  # collimated
+    assert res["f-preserving"]["min_rel"] > 0.5 > res["PLUTO"]["min_rel"]       # PLUTO's undershoot
