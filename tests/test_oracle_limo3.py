@@ -173,3 +173,36 @@ def test_limo3_shock_tube_convergence_rate(orc, which):
         errs.append(np.abs(out["E"][0, 0] - Er.reshape(N, -1).mean(axis=1)).mean())
     slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
     assert -0.65 <= slope <= -0.35, (slope, errs)
+
+
+def _pi_beta(out):
+    """Pi = (1 - xi) E / 2 and beta_x = (3 xi - 1) F_x E / (2 |F|) (Sect. 3.1)."""
+    E, Fx, Fy = out["E"][0, 0], out["Fx"][0, 0], out["Fy"][0, 0]
+    F = np.sqrt(Fx * Fx + Fy * Fy)
+    f = np.minimum(F / E, 1.0)
+    xi = (3 + 4 * f * f) / (5 + 2 * np.sqrt(4 - 3 * f * f))
+    return (1 - xi) * E / 2, np.where(F > 0, (3 * xi - 1) * Fx * E / (2 * np.where(F > 0, F, 1.0)), 0.0)
+
+
+def test_pluto_fallback_oscillates_with_limo3_in_the_second_tube(orc):
+    """Sect. 3.1, second tube (f = 1 on both sides) at 2^8 cells with LimO3:
+    the PLUTO face treatment makes Pi and beta_x oscillate between the
+    contact-like discontinuity and the right-going shock, the f-preserving
+    fix does not.  Measured as the total variation over x in (-1.5, 3.5),
+    where the converged solution is flat (the 2^15-cell reference varies by
+    1e-4 there): PLUTO's is 21x (Pi) and 4x (beta_x) the f-preserving one."""
+    N = 256
+    x = -20 + (np.arange(N) + 0.5) * 40 / N
+    w = (x > -1.5) & (x < 3.5)
+    tv = {}
+    for recon in (0, 1):
+        p = I.make_shock_tube(2, N=N)
+        p.limiter, p.recon = 1, recon
+        out, _ = orc.Oracle(p).run(p.fields, p.dt, p.steps, rk2=True)
+        Pi, beta = _pi_beta(out)
+        tv[recon] = (np.abs(np.diff(Pi[w])).sum(), np.abs(np.diff(beta[w])).sum())
+    ref = np.load(os.path.join(GOLDEN, "shock_tube_reference_2.npz"))
+    Pr, _ = _pi_beta({k: ref[k].reshape(N, -1).mean(axis=1)[None, None] for k in ("E", "Fx", "Fy")})
+    assert np.abs(np.diff(Pr[w])).sum() < 1e-3
+    assert tv[0][0] < 3e-3 and tv[1][0] > 5 * tv[0][0], tv
+    assert tv[1][1] > 2 * tv[0][1], tv
