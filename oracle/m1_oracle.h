@@ -14,6 +14,13 @@
  *
  * Array layout: cell (i, j, k) along (d0, d1, d2) lives at ((k*n1)+j)*n0+i.
  * F components are in the local orthonormal basis of the grid.
+ *
+ * Parity unpinned: the optical depth of a curvilinear cell in the signal-
+ * speed limiter, tau = rho chi max_d h_d with h_d the cell's metric extent
+ * (cell_tau in transport.c).  The method gives tau per cell without saying
+ * which length a cylindrical or spherical cell takes; the extents are a
+ * reading, and no value the paper fixes checks them (the same extents in
+ * the time-step rule are pinned by hand-worked values).
  */
 #ifndef M1_ORACLE_H
 #define M1_ORACLE_H
