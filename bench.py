@@ -330,7 +330,7 @@ def _log10_opacity(m1, torch, ctx, rho, T):
 
 def mlp_gain(m1, torch, I, weights, table_sizes=(128, 512, 2048, 4096), K=20, W=20):
     """What the trained network changes against the bilinear table it
-    replaces, measured on the device (the table lookup is the judge):
+    replaces, measured on the device (the table lookup is the reference):
 
     * model bytes: network parameters (FP32 master), its packed inference
       buffer, and the two 128 x 128 FP32 tables;

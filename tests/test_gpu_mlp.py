@@ -108,7 +108,7 @@ def trained():
 def test_training_reaches_target(orc, trained):
     m1, s, tab, held, th, norm, rep = trained
     assert rep["max_rel_err_P"] <= 1e-3 and rep["max_rel_err_R"] <= 1e-3, rep
-    # judge independently with the oracle's bilinear lookup on the held-out set
+    # checked independently with the oracle's bilinear lookup on the held-out set
     n = held.shape[0]
     lr, lt = held[:, 0].astype(np.float64), held[:, 1].astype(np.float64)
     rho = torch.from_numpy(10 ** (lr - tab["lr_off"])).to("cuda")
@@ -144,7 +144,7 @@ def test_c4_spherical_run_with_network(orc, trained):
 
 def test_network_gain_over_table(orc, trained):
     """What the trained network changes against the bilinear table it stands
-    in for (the table lookup stays the judge of its error):
+    in for (the table lookup stays the reference for its error):
 
     * gained: a model 7x smaller than the two FP32 tables (parameters) and
       smooth: the slope d log10 kappa / d log10 T of the table jumps at every
