@@ -355,7 +355,7 @@ def mlp_gain(m1, torch, I, weights, table_sizes=(128, 512, 2048, 4096), K=20, W=
     sm = m1.Solver(p, "p64")
     m1.m1_set_opacity_mlp(sm.ctx, weights["theta"], weights["norm"])
     out = {"model_bytes": {"network_parameters_fp32": 4 * m1.M1_MLP_NPARAM,
-                           "network_packed_inference_buffer": 4 * 8704,
+                           "network_packed_inference_buffer": 4 * 9860,
                            "table_two_128x128_fp32": 2 * 4 * tab["nr"] * tab["nt"]}}
 
     def compare(rho, T, lr, lt):

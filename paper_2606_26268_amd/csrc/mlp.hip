@@ -58,18 +58,21 @@ static inline float host_bf16_value(unsigned short b)
     return f;
 }
 
-// Inference entries of the packed network from the flat parameters: the
-// split fragments of A2 = s W2 (s = MLP_TANH_SCALE).  16 blocks of 256
-// threads, one W2 element each.
+// The inference form's LDS image in the packed network, from the flat
+// parameters: the split fragments of A2 = s W2 (s = MLP_TANH_SCALE), one W2
+// element per thread, and the layer-1, bias and output entries
+// (mlp_image_entry).  16 blocks of 256 threads.
 __global__ void __launch_bounds__(256) k_mlp_pack_infer(const float *theta, float *pk)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int u = t >> 6, k = t & 63;
+    MlpShared &img = *reinterpret_cast<MlpShared *>(pk + MLP_OFF_IMG);
     const float v = MLP_TANH_SCALE * theta[P_W2 + t];
     const __bf16 h = to_bf16(v);
     const __bf16 l = to_bf16(v - float(h));
-    reinterpret_cast<unsigned short *>(pk + MLP_OFF_A2HI)[frag_slot(u, k)] = __builtin_bit_cast(unsigned short, h);
-    reinterpret_cast<unsigned short *>(pk + MLP_OFF_A2LO)[frag_slot(u, k)] = __builtin_bit_cast(unsigned short, l);
+    reinterpret_cast<unsigned short *>(&img.w2[0][0][0][0])[frag_slot(u, k)] = __builtin_bit_cast(unsigned short, h);
+    reinterpret_cast<unsigned short *>(&img.w2[1][0][0][0])[frag_slot(u, k)] = __builtin_bit_cast(unsigned short, l);
+    mlp_image_entry(theta + P_W1, theta + P_B1, theta + P_B2, theta + P_W3, img, t);
 }
 
 static void host_pack(const float *th, const double *norm, std::vector<float> &pk)

@@ -23,6 +23,18 @@ namespace m1 {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// LDS image of the inference form (see the inference section below); the
+// packed network holds it at MLP_OFF_IMG, 16-byte words copied as they are
+struct MlpShared {
+    bf16x8 w2[2][2][4][64];   // A2 fragments [hi, lo][mt][ks][lane], 16 KiB
+    bf16x8 w1[2][64];         // layer-1 A operand: [mt][lane]
+    bf16x8 c2[2][64];         // s b2 as an A operand [mt][lane]: K slots 0..2 its three bfloat16 pieces
+    float2 ep[2][2][16];      // [g][mt][i]: -2 W3[0], -2 W3[1] of the slot's unit
+    float w3sum[2];           // sum over units of W3[0], W3[1]
+    float pad[2];             // to a whole number of 16-byte words
+};
+static_assert(sizeof(MlpShared) % 16 == 0, "MlpShared is staged in 16-byte words");
+
 // Packed network (float words):
 //   [0, 128)      W1[64][2]
 //   [128, 192)    b1[64]
@@ -33,16 +45,20 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 //   [390, 394)    norm: mean_P, std_P, mean_R, std_R
 //   [512, 2560)   W2 hi fragments: bf16 [mt 2][ks 4][lane 64][8]
 //   [2560, 4608)  W2 lo fragments, same order
-//   [4608, 6656)  A2 hi fragments, A2 = s W2 (s = MLP_TANH_SCALE), same order
-//   [6656, 8704)  A2 lo fragments
-// (A2 serves the inference form below, whose second layer delivers the
-// scaled pre-activation s (W2 h1 + b2) = A2 h1 + s b2 directly)
-constexpr int MLP_PACK_FLOATS = 8704;
+//   [4608, 9860)  the inference form's LDS image (MlpShared below), staged
+//                 by every block as it is: A2 hi and lo fragments
+//                 (A2 = s W2, s = MLP_TANH_SCALE, same order as W2), the
+//                 layer-1 and bias operands and the output weights
+// (the image serves the inference form below, whose second layer delivers
+// the scaled pre-activation s (W2 h1 + b2) = A2 h1 + s b2 directly; it is
+// derived on the device from the flat parameters whenever they change)
 constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 128, MLP_OFF_B2 = 192, MLP_OFF_W3 = 256;
 constexpr int MLP_OFF_B3 = 384, MLP_OFF_WS = 386, MLP_OFF_NORM = 390;
 constexpr int MLP_OFF_W2HI = 512, MLP_OFF_W2LO = 2560;
-constexpr int MLP_OFF_A2HI = 4608, MLP_OFF_A2LO = 6656;
+constexpr int MLP_OFF_IMG = 4608;
 constexpr float MLP_TANH_SCALE = 2.8853900817779268f;   // 2 / ln 2
+constexpr int MLP_PACK_FLOATS = MLP_OFF_IMG + int(sizeof(MlpShared) / 4);
+static_assert(MLP_OFF_IMG % 4 == 0 && MLP_PACK_FLOATS == 9860, "packed network layout");
 
 __device__ __forceinline__ float fast_tanh(float x)
 {
@@ -263,29 +279,21 @@ __host__ __device__ constexpr int mlp_l1_unit(int mt, int r)
     return 32 * mt + (r & 0x13) + ((r & 4) << 1) + ((r & 8) >> 1);
 }
 
-struct MlpShared {
-    bf16x8 w2[2][2][4][64];   // A2 fragments [hi, lo][mt][ks][lane], 16 KiB
-    bf16x8 w1[2][64];         // layer-1 A operand: [mt][lane]
-    bf16x8 c2[2][64];         // s b2 as an A operand [mt][lane]: K slots 0..2 its three bfloat16 pieces
-    float2 ep[2][2][16];      // [g][mt][i]: -2 W3[0], -2 W3[1] of the slot's unit
-    float w3sum[2];           // sum over units of W3[0], W3[1]
-};
-
-__device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, int tid, int nthreads)
+// Entries of the LDS image derived from the flat parameters (W1 [64][2],
+// b1 [64], b2 [64], W3 [2][64] of the flat vector), for thread t of a
+// 4096-thread pack grid (the A2 fragments are written elsewhere): t < 128
+// the layer-1 operand, 128 <= t < 256 the bias operand, 256 <= t < 320 the
+// output weights, and the wavefront 320 <= t < 384 (which runs this branch
+// whole) the sums of W3 in a fixed order.
+__device__ __forceinline__ void mlp_image_entry(const float *W1, const float *b1, const float *b2, const float *W3,
+                                                MlpShared &img, int t)
 {
-    const bf16x8 *hi = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_A2HI);
-    const bf16x8 *lo = reinterpret_cast<const bf16x8 *>(packed + MLP_OFF_A2LO);
-    bf16x8 *dst = &sh.w2[0][0][0][0];
-    for (int q = tid; q < 512; q += nthreads) {
-        dst[q] = hi[q];
-        dst[512 + q] = lo[q];
-    }
-    for (int q = tid; q < 128; q += nthreads) {
+    if (t < 128) {
         // layer-1 A operand of lane l in tile mt: row l % 32, K = 8 (l / 32) + e
-        const int mt = q >> 6, l = q & 63, g = l >> 5;
+        const int mt = t >> 6, l = t & 63, g = l >> 5;
         const int u = mlp_l1_unit(mt, l & 31);
-        const float w = MLP_TANH_SCALE * packed[MLP_OFF_W1 + 2 * u + g];
-        const float bias = MLP_TANH_SCALE * packed[MLP_OFF_B1 + u];
+        const float w = MLP_TANH_SCALE * W1[2 * u + g];
+        const float bias = MLP_TANH_SCALE * b1[u];
         unsigned whm, whl, bhm, bhl;
         split3_bf16(w, whm, whl);
         split3_bf16(bias, bhm, bhl);
@@ -297,42 +305,47 @@ __device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, in
         v.y = wm | (wh << 16);
         v.z = wl | (wm << 16);
         v.w = g ? bl : (bh | (bm << 16));
-        sh.w1[mt][l] = __builtin_bit_cast(bf16x8, v);
-    }
-    // the output layer takes h2 = 1 - 2 r (r = 1 / (1 + 2^z)) as
-    // sum W3 - 2 sum W3 r: weights -2 W3 per unit, the sum once per output
-    for (int q = tid; q < 64; q += nthreads) {
-        const int g = q >> 5, mt = (q >> 4) & 1, i = q & 15;
-        const int u = MlpWave::unit(mt, i, g);
-        sh.ep[g][mt][i] = make_float2(-2.0f * packed[MLP_OFF_W3 + u], -2.0f * packed[MLP_OFF_W3 + 64 + u]);
-    }
-    // the accumulator's start s b2 enters through one more product, A = s b2
-    // in K slots 0..2 (exact three-piece split) against B = 1 in those slots
-    for (int q = tid; q < 128; q += nthreads) {
-        const int mt = q >> 6, l = q & 63;
+        img.w1[mt][l] = __builtin_bit_cast(bf16x8, v);
+    } else if (t < 256) {
+        // the accumulator's start s b2 enters through one more product, A =
+        // s b2 in K slots 0..2 (exact three-piece split) against B = 1 there
+        const int q = t - 128, mt = q >> 6, l = q & 63;
         unsigned hm, hl;
-        split3_bf16(MLP_TANH_SCALE * packed[MLP_OFF_B2 + 32 * mt + (l & 31)], hm, hl);
+        split3_bf16(MLP_TANH_SCALE * b2[32 * mt + (l & 31)], hm, hl);
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (l < 32) {
             v.x = hm;              // K 0, 1: c2 hi, c2 mid
             v.y = hl >> 16;        // K 2: c2 lo
         }
-        sh.c2[mt][l] = __builtin_bit_cast(bf16x8, v);
-    }
-    if (tid < 64) {
-        // fixed-order butterfly over the first wavefront: the same sums in
-        // every block
-        float s0 = packed[MLP_OFF_W3 + tid], s1 = packed[MLP_OFF_W3 + 64 + tid];
+        img.c2[mt][l] = __builtin_bit_cast(bf16x8, v);
+    } else if (t < 320) {
+        // the output layer takes h2 = 1 - 2 r (r = 1 / (1 + 2^z)) as
+        // sum W3 - 2 sum W3 r: weights -2 W3 per unit, the sum once per output
+        const int q = t - 256, g = q >> 5, mt = (q >> 4) & 1, i = q & 15;
+        const int u = MlpWave::unit(mt, i, g);
+        img.ep[g][mt][i] = make_float2(-2.0f * W3[u], -2.0f * W3[64 + u]);
+    } else if (t < 384) {
+        const int lane = t - 320;
+        float s0 = W3[lane], s1 = W3[64 + lane];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             s0 += __shfl_xor(s0, o);
             s1 += __shfl_xor(s1, o);
         }
-        if (tid == 0) {
-            sh.w3sum[0] = s0;
-            sh.w3sum[1] = s1;
+        if (lane == 0) {
+            img.w3sum[0] = s0;
+            img.w3sum[1] = s1;
+            img.pad[0] = img.pad[1] = 0.0f;
         }
     }
+}
+
+// Stage the inference form's LDS image: a copy of 16-byte words.
+__device__ __forceinline__ void mlp_stage(const float *packed, MlpShared &sh, int tid, int nthreads)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(packed + MLP_OFF_IMG);
+    uint4 *dst = reinterpret_cast<uint4 *>(&sh);
+    for (int q = tid; q < int(sizeof(MlpShared) / 16); q += nthreads) dst[q] = src[q];
 }
 
 __device__ __forceinline__ void mlp_forward_shared(const float *p, const MlpShared &sh, float x0, float x1, int lane,
