@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256, 4) k_implicit_mlp(IArgs<R> a)
         mlp_opacity_shared(a.op, sh, rho, float(T1), lane, kP, kR);
         if (live) {
             at(a.rkp, base, t) = R(rho * kP);
-            at(a.tau, base, t) = R(rho * (kR + float(a.op.sigma))) * hm;
+            at(a.tau, base, t) = R(rho * (kR + a.op.f32.sigma)) * hm;
         }
     }
 }
@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(256) k_opacity_init_mlp(IArgs<R> a)
         mlp_opacity_shared(a.op, sh, rho, float(T), lane, kP, kR);
         if (live) {
             a.rkp[id] = R(rho * kP);
-            a.tau[id] = R(rho * (kR + float(a.op.sigma))) * cell_hmax(a.m, a.ndim, i, j, k);
+            a.tau[id] = R(rho * (kR + a.op.f32.sigma)) * cell_hmax(a.m, a.ndim, i, j, k);
         }
     }
 }

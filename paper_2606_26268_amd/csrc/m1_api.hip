@@ -469,6 +469,7 @@ m1_status m1_set_opacity_model(m1_ctx *c, int kind, const double *p)
     } else {
         return fail(M1_EINVAL, "m1_set_opacity_model: unknown kind");
     }
+    opacity_f32(c->op);
     return refresh(c);
 }
 
@@ -506,6 +507,7 @@ m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1
     c->op.tab_kP = c->table_dev;
     c->op.tab_kR = c->table_dev + n;
     c->op.sigma = sigma;
+    opacity_f32(c->op);
     return refresh(c);
 }
 

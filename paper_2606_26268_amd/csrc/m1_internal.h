@@ -81,7 +81,26 @@ struct OpacityParams {
     const float *tab_kP, *tab_kR;               // device
     const float *mlp;                           // device, packed (see mlp.hip)
     double norm[4];
+    // FP32 copies of the table axes and sigma for the network's FP32
+    // arithmetic (rounded once on the host instead of per wavefront)
+    struct {
+        float lr0, lr1, lt0, lt1, lr_off, lt_off, lr_inv, lt_inv, sigma;
+    } f32;
 };
+
+// refresh OpacityParams::f32 from the FP64 fields
+inline void opacity_f32(OpacityParams &o)
+{
+    o.f32.lr0 = float(o.lr0);
+    o.f32.lr1 = float(o.lr1);
+    o.f32.lt0 = float(o.lt0);
+    o.f32.lt1 = float(o.lt1);
+    o.f32.lr_off = float(o.lr_off);
+    o.f32.lt_off = float(o.lt_off);
+    o.f32.lr_inv = float(o.lr_inv);
+    o.f32.lt_inv = float(o.lt_inv);
+    o.f32.sigma = float(o.sigma);
+}
 
 // multigroup parameters (constant group opacities, interior band edges)
 struct GroupParams {

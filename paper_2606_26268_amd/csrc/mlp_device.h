@@ -190,12 +190,13 @@ struct MlpWave {
         // log10 through the hardware log2 (the network inputs carry FP32
         // rounding in any case), clamped to the table axes
         constexpr float LOG10_2 = 0.30102999566398120f;
-        float lr = __builtin_amdgcn_logf(rho) * LOG10_2 + float(op.lr_off);
-        float lt = __builtin_amdgcn_logf(T) * LOG10_2 + float(op.lt_off);
-        lr = __builtin_fminf(__builtin_fmaxf(lr, float(op.lr0)), float(op.lr1));
-        lt = __builtin_fminf(__builtin_fmaxf(lt, float(op.lt0)), float(op.lt1));
-        x0 = 2.0f * (lr - float(op.lr0)) * float(op.lr_inv) - 1.0f;
-        x1 = 2.0f * (lt - float(op.lt0)) * float(op.lt_inv) - 1.0f;
+        const auto &q = op.f32;
+        float lr = __builtin_amdgcn_logf(rho) * LOG10_2 + q.lr_off;
+        float lt = __builtin_amdgcn_logf(T) * LOG10_2 + q.lt_off;
+        lr = __builtin_fminf(__builtin_fmaxf(lr, q.lr0), q.lr1);
+        lt = __builtin_fminf(__builtin_fmaxf(lt, q.lt0), q.lt1);
+        x0 = 2.0f * (lr - q.lr0) * q.lr_inv - 1.0f;
+        x1 = 2.0f * (lt - q.lt0) * q.lt_inv - 1.0f;
     }
 
     __device__ __forceinline__ void opacity(const OpacityParams &op, float rho, float T, int lane, float &kP,
