@@ -186,7 +186,9 @@ typedef struct {
 
 typedef struct m1_ctx m1_ctx;
 
-/* Fill *p with defaults for reduced speed of light c_hat. */
+/* Fill *p with defaults for reduced speed of light c_hat: c = c_hat (the
+ * reduced-c factor of Sect. 2.7 off), a_rad = 1, gamma = 5/3, FP64, the
+ * f-preserving face fix with HLL (Sect. 2.5), PLM, Euler steps.  Host only. */
 m1_status m1_params_default(double c_hat, m1_params *p);
 
 /* Create a context for grid g (copied) in geometry geom with reduced speed
@@ -200,13 +202,17 @@ m1_status m1_params_default(double c_hat, m1_params *p);
 m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_params *p,
                     m1_ctx **out);
 
-/* Free the context and every library-owned buffer; never the caller's. */
+/* Free the context and every library-owned buffer; never the caller's.
+ * (Resource management: no passage of the paper.) */
 m1_status m1_destroy(m1_ctx *ctx);
 
-/* Enqueue all further work on hipStream_t `stream` (NULL: null stream). */
+/* Enqueue all further work on hipStream_t `stream` (NULL: null stream).
+ * (Execution plumbing: no passage of the paper.) */
 m1_status m1_set_stream(m1_ctx *ctx, void *stream);
 
-/* Bind caller-owned device arrays (must outlive the binding) and allocate
+/* Bind the state of Sect. 2.1 and 2.8 (radiation E_r, F_r; gas density,
+ * momentum and total energy) as caller-owned device arrays (must outlive
+ * the binding) and allocate
  * the library's scratch (transported E*, F*, opacity caches, reduction
  * buffers).  Evaluates the opacity cache from the current gas state.
  * M1_EINVAL on a NULL or non-256-byte-aligned pointer.  M1_ENOMEM when an
@@ -234,15 +240,21 @@ m1_status m1_set_opacity_table(m1_ctx *ctx, int nr, int nt, double lr_min, doubl
                                const float *log10_kP, const float *log10_kR, double sigma);
 
 /* Use the MLP surrogate in place of the table (the table must be set: its
- * axes and offsets define the network's input scaling). */
+ * axes and offsets define the network's input scaling).  The surrogate is
+ * not part of the paper's method: it stands in for the tabulated mean
+ * opacities kappa_P, kappa_R (Sect. 2.1, Sect. 3.7), and the table it was
+ * trained on stays the reference for its error. */
 m1_status m1_set_opacity_mlp(m1_ctx *ctx, const m1_mlp *w);
 
-/* Train the surrogate on the GPU (see m1_train_cfg); on success the trained
- * network becomes the context's opacity source.  Synchronous. */
+/* Train the surrogate on the GPU (see m1_train_cfg) against the bound
+ * table (Sect. 3.7 tabulated opacities; the surrogate itself is an
+ * addition, see m1_set_opacity_mlp); on success the trained network
+ * becomes the context's opacity source.  Synchronous. */
 m1_status m1_mlp_train(m1_ctx *ctx, const m1_train_cfg *cfg, m1_train_report *rep);
 
 /* Copy the current network parameters to host theta (M1_MLP_NPARAM floats)
- * and norm[4].  Synchronous. */
+ * and norm[4].  Synchronous.  (Surrogate bookkeeping, see
+ * m1_set_opacity_mlp.) */
 m1_status m1_mlp_get(m1_ctx *ctx, float *theta, double *norm);
 
 /* Loss and gradient of the surrogate (parameters theta, host float32
@@ -250,12 +262,14 @@ m1_status m1_mlp_get(m1_ctx *ctx, float *theta, double *norm);
  * a positive multiple of 64) against the bound table, computed by the
  * training kernels: grad (host, M1_MLP_NPARAM floats), *loss.  theta
  * becomes the context's network; the normalisation is the one set by
- * m1_set_opacity_mlp or m1_mlp_train.  Synchronous. */
+ * m1_set_opacity_mlp or m1_mlp_train.  Synchronous.  (The surrogate's
+ * training gradient, checked against the oracle; see m1_set_opacity_mlp.) */
 m1_status m1_mlp_gradient(m1_ctx *ctx, const float *samples, long n, const float *theta, float *grad,
                           double *loss);
 
 /* Evaluate the active opacity source on n device points: rho, T (double) ->
- * kP, kR (double).  Asynchronous. */
+ * kP, kR (double), the Planck and Rosseland means of Sect. 2.1.  n = 0 is
+ * a no-op.  Asynchronous. */
 m1_status m1_opacity_eval(m1_ctx *ctx, long n, const double *rho, const double *T, double *kP,
                           double *kR);
 
@@ -300,7 +314,8 @@ m1_status m1_step_implicit(m1_ctx *ctx, double dt);
 m1_status m1_set_groups(m1_ctx *ctx, int m, const double *edges, const double *kP, const double *kR,
                         double sigma);
 
-/* Ghost state of a M1_BC_FIXED side: dir 0..2, side 0 (lower) or 1 (upper),
+/* Ghost state of a M1_BC_FIXED side (the injected beam of the shadow test,
+ * Sect. 3.3): dir 0..2, side 0 (lower) or 1 (upper),
  * state = (E, Fx, Fy, Fz) in the grid's local basis (host memory, copied),
  * E > 0 and |F| <= E.  Every fixed side needs its state before the first
  * m1_step_explicit (M1_ESTATE otherwise).  The optical depth of a fixed
@@ -350,15 +365,18 @@ m1_status m1_step_noalloc(m1_ctx *ctx, const m1_fields *f, double dt);
 m1_status m1_step_rk2(m1_ctx *ctx, double dt);
 
 /* Device pointers of the library's transported state E*, Fx*, Fy*, Fz*
- * (valid after m1_step_explicit; owned by the library).  Gray states only
+ * (the state between the explicit and the implicit part of the Sect. 2.4
+ * step list; valid after m1_step_explicit; owned by the library).  Gray states only
  * (M1_ENOTSUP with groups). */
 m1_status m1_transported(m1_ctx *ctx, void **E, void **Fx, void **Fy, void **Fz);
 
-/* Re-evaluate the opacity cache from the bound gas state (call after the
- * caller changes rho, m or E_g outside the library). */
+/* Re-evaluate the opacity cache (rho kappa_P and the optical depth of the
+ * Sect. 2.6 limiter) from the bound gas state (call after the caller
+ * changes rho, m or E_g outside the library). */
 m1_status m1_refresh_opacity(m1_ctx *ctx);
 
-/* Wait for the stream; reports a deferred device error as M1_EDEVICE. */
+/* Wait for the stream; reports a deferred device error as M1_EDEVICE.
+ * (Execution plumbing: no passage of the paper.) */
 m1_status m1_sync(m1_ctx *ctx);
 
 /* Synchronous reduction of the bound state (see m1_diag): the conserved
@@ -366,7 +384,8 @@ m1_status m1_sync(m1_ctx *ctx);
  * counters of the positivity and f <= 1 fix-ups (Sect. 3.1, Sect. 2.1). */
 m1_status m1_diagnostics(m1_ctx *ctx, m1_diag *out);
 
-/* Text of the last error raised on the calling thread ("" if none). */
+/* Text of the last error raised on the calling thread ("" if none).
+ * (Error reporting: no passage of the paper.) */
 const char *m1_last_error(void);
 
 #ifdef __cplusplus
