@@ -347,6 +347,9 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
         c->faces[d].assign(g->faces[d], g->faces[d] + g->n[d] + 1);
     }
     hipGetDevice(&c->device);
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0)
+        c->cus = cu;
     noalloc_setup(c->device);
     c->op.kind = OPK_CONST;
     HostMetric M;

@@ -136,6 +136,7 @@ struct m1_ctx {
     std::vector<double> faces[3];
     hipStream_t stream = nullptr;
     int device = 0;
+    int cus = 256;            // compute units of the device (pairing of transport blocks)
 
     // metric arrays (one allocation) in both precisions
     void *metric_buf = nullptr;

@@ -322,7 +322,7 @@ __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
 // the 32 x 8 tile in FP64 (the 512-thread block spilled).
 template <typename R, int GEOM, bool GENERAL, int TYB, bool LIMO3 = false>
 __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? (LIMO3 ? 2 : 3) : 4) : 1))
-    k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks)
+    k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks, int cus)
 {
     using T = Tile<TYB>;
     constexpr int TX = T::TX, TY = T::TY, HX = T::HX, HY = T::HY, NT = T::NT;
@@ -508,7 +508,24 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
         }
     }
 
+    // Default FP32 kernel: blocks b and b + cus share a compute unit (each
+    // XCD hands out its blocks in order, one per compute unit before the
+    // second), and the wave arbiter favours the older block: left alone, the
+    // first block on a unit finished its chunk in 70 % of the second's time
+    // (measured on the 192x96x192 grid), and the second then ran alone at
+    // half occupancy.  The two alternate their wave priority every plane and
+    // stay level (3-4 % faster transport with one round of blocks, 1 % with
+    // several).  FP64 blocks run one per unit and the general FP32 kernel
+    // three; for those the alternation did not pay (1-6 % slower).
+    constexpr bool ALTERNATE = sizeof(R) == 4 && !GENERAL;
+    const int prio_grp = (int(blockIdx.x) / cus) & 1;
     for (int k = z0; k < z1; ++k) {
+        if constexpr (ALTERNATE) {
+            if (((k - z0) ^ prio_grp) & 1)
+                __builtin_amdgcn_s_setprio(1);
+            else
+                __builtin_amdgcn_s_setprio(0);
+        }
         // prefetch the plane entering the window and this plane's halo
         R Qn[4];
         load4(a, zlin(k + 3, col), Qn);
@@ -681,7 +698,7 @@ static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, long max_ro
     const int nblocks = tiles_x * tiles_y * ((c->n[2] + nz - 1) / nz);
     const int launched = ((nblocks + 7) / 8) * 8;
     hipLaunchKernelGGL((k_transport3d<R, GEOM, GENERAL, TYB, LIMO3>), dim3(launched, ngrp), dim3(NT), 0, c->stream, a, nz,
-                       tiles_x, tiles_y, nblocks);
+                       tiles_x, tiles_y, nblocks, c->cus);
     return true;
 }
 
