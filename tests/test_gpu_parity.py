@@ -388,3 +388,34 @@ def test_pulse_long_run(orc, precision):
         assert d.sum() <= tol * (np.abs(ref["F" + c]).sum() / p.c_hat), c
     es = (p.c / p.c_hat) * np.abs(ref["E"]).max()
     assert np.abs(got["Eg"] - ref["Eg"]).max() <= 10 * tol * es
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_injected_unrealizable_cells_are_fixed_like_the_oracle(orc, precision):
+    """Host-forced fix-ups: two cells of a 3D random state get |F| = 3 E and
+    |F| = 1.5 E (f > 1, unrealizable), and the energy floor is raised to the
+    0.5 % quantile of E so that the positivity floor acts in a few cells.
+    After two steps the fix-up counters (energy floor, f <= 1 after transport
+    and after the implicit step) equal the oracle's, the first two non-zero
+    (2 and 2), and the state matches the oracle as usual."""
+    p = _problem(I.CARTESIAN, (24, 16, 12), 3, seed=77)
+    E = p.fields["E"]
+    for idx, fac in (((3, 5, 7), 3.0), ((9, 2, 20), 1.5)):
+        fn = np.sqrt(p.fields["Fx"][idx] ** 2 + p.fields["Fy"][idx] ** 2 + p.fields["Fz"][idx] ** 2)
+        scale = fac * E[idx] / fn
+        for k in ("Fx", "Fy", "Fz"):
+            p.fields[k][idx] *= scale
+    p.e_floor = float(np.quantile(E, 0.005))
+    o = orc.Oracle(p)
+    dt = o.max_dt(0.4)
+    ref, cnt = o.run(p.fields, dt, 2)
+    got, diag = run_gpu(p, precision, 2, dt=dt)
+    say(f"  injected fix-ups: oracle {list(cnt[:3])}, GPU {diag['counters'][:3]}")
+    assert cnt[0] > 0 and cnt[1] > 0, cnt
+    if precision == "p64":
+        assert diag["counters"][:3] == list(cnt[:3])
+        assert_close(got, ref, TOL_P64, label="injected p64")
+    else:
+        # FP32 rounding can move a cell across the floor: counts within one
+        assert all(abs(a - b) <= 1 for a, b in zip(diag["counters"][:3], cnt[:3])), (diag["counters"], cnt)
+        assert_close_f32(got, ref, fp32_response(orc, p, 2, dt=dt), label="injected f32")
