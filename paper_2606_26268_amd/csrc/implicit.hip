@@ -50,19 +50,37 @@ __device__ __forceinline__ R cell_hmax(const Metric<R> &m, int ndim, int i, int 
     return h;
 }
 
-__device__ __forceinline__ double gas_T(double rho, double mx, double my, double mz, double Eg,
-                                        double gamma)
-{
-    const double Cv = rho / (gamma - 1.0);
-    return (Eg - 0.5 * (mx * mx + my * my + mz * mz) / rho) / Cv;
-}
-
 // Gas temperature with the reciprocal density supplied:
 // T = (E_g - |m|^2 / (2 rho)) (gamma - 1) / rho.
+// Written with explicit fused multiply-adds, so that every inlined copy
+// rounds the same way whatever the compiler would contract around it.
 __device__ __forceinline__ double gas_T_r(double inv_rho, double mx, double my, double mz, double Eg,
                                           double gm1)
 {
-    return (Eg - 0.5 * (mx * mx + my * my + mz * mz) * inv_rho) * (gm1 * inv_rho);
+    const double m2 = __builtin_fma(mx, mx, __builtin_fma(my, my, mz * mz));
+    return __builtin_fma(-0.5 * inv_rho, m2, Eg) * (gm1 * inv_rho);
+}
+
+// Gas temperature of a stored state, in exactly the arithmetic the implicit
+// step uses for the temperature at which it refreshes the opacity cache, so
+// that a cache derived from a stored state (binding, refresh) equals the one
+// the step left: a state saved and bound again continues bit for bit.
+__device__ __forceinline__ double gas_T_stored(double rho, double mx, double my, double mz, double Eg, double gm1)
+{
+    return gas_T_r(Num<double>::rcp(rho), mx, my, mz, Eg, gm1);
+}
+
+// One opacity-cache entry: the absorption rate rho kappa_P and the cell's
+// optical depth rho (kappa_R + sigma) h.  Contraction is off here, so the
+// sum cannot fuse with the last product of the opacity evaluation in one
+// kernel and not in another: the implicit step and the refresh from a stored
+// state write the same bits, and a saved state bound again continues exactly.
+template <typename R, typename K>
+__device__ __forceinline__ void cache_entry(K rho, K kP, K kR, K sigma, R hm, R &rkp, R &tau)
+{
+#pragma clang fp contract(off)
+    rkp = R(rho * kP);
+    tau = R(rho * (kR + sigma)) * hm;
 }
 
 // Element t of the run of cells starting at base: the block's base offset is
@@ -172,8 +190,7 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
         const R rho = R(at(a.rho, base, t));
         R kP, kR;
         opacity_analytic<R, OPK>(a.op, rho, R(T1), kP, kR);
-        at(a.rkp, base, t) = rho * kP;
-        at(a.tau, base, t) = rho * (kR + R(a.op.sigma)) * hm;
+        cache_entry(rho, kP, kR, R(a.op.sigma), hm, at(a.rkp, base, t), at(a.tau, base, t));
     }
 }
 
@@ -207,8 +224,7 @@ __global__ void __launch_bounds__(256, 4) k_implicit_mlp(IArgs<R> a)
         float kP, kR;
         mlp_opacity_shared(a.op, sh, rho, float(T1), lane, kP, kR);
         if (live) {
-            at(a.rkp, base, t) = R(rho * kP);
-            at(a.tau, base, t) = R(rho * (kR + a.op.f32.sigma)) * hm;
+            cache_entry(rho, kP, kR, a.op.f32.sigma, hm, at(a.rkp, base, t), at(a.tau, base, t));
         }
     }
 }
@@ -548,12 +564,11 @@ __global__ void __launch_bounds__(256) k_opacity_init(IArgs<R> a)
     if (id >= N) return;
     int i, j, k;
     a.ix.split(id, i, j, k);
-    const double T = gas_T(a.rho[id], a.mx[id], a.my[id], a.mz[id], a.Eg[id], a.k.gamma);
+    const double T = gas_T_stored(a.rho[id], a.mx[id], a.my[id], a.mz[id], a.Eg[id], a.k.gm1);
     const R rho = R(a.rho[id]);
     R kP, kR;
     opacity_analytic<R, OPK>(a.op, rho, R(T), kP, kR);
-    a.rkp[id] = rho * kP;
-    a.tau[id] = rho * (kR + R(a.op.sigma)) * cell_hmax(a.m, a.ndim, i, j, k);
+    cache_entry(rho, kP, kR, R(a.op.sigma), cell_hmax(a.m, a.ndim, i, j, k), a.rkp[id], a.tau[id]);
 }
 
 template <typename R>
@@ -571,13 +586,12 @@ __global__ void __launch_bounds__(256) k_opacity_init_mlp(IArgs<R> a)
         const int idc = live ? id : N - 1;
         int i, j, k;
         a.ix.split(idc, i, j, k);
-        const double T = gas_T(a.rho[idc], a.mx[idc], a.my[idc], a.mz[idc], a.Eg[idc], a.k.gamma);
+        const double T = gas_T_stored(a.rho[idc], a.mx[idc], a.my[idc], a.mz[idc], a.Eg[idc], a.k.gm1);
         const float rho = float(a.rho[idc]);
         float kP, kR;
         mlp_opacity_shared(a.op, sh, rho, float(T), lane, kP, kR);
         if (live) {
-            a.rkp[id] = R(rho * kP);
-            a.tau[id] = R(rho * (kR + a.op.f32.sigma)) * cell_hmax(a.m, a.ndim, i, j, k);
+            cache_entry(rho, kP, kR, a.op.f32.sigma, cell_hmax(a.m, a.ndim, i, j, k), a.rkp[id], a.tau[id]);
         }
     }
 }

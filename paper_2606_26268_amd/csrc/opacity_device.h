@@ -23,9 +23,15 @@ template <> struct OMath<float> {
 };
 
 // Table coordinates (log10 rho + lr_off, log10 T + lt_off) clamped to the axes.
+// Here and in the interpolation below contraction is off: inlined into
+// different kernels, the sums would otherwise fuse with neighbouring products
+// (the logarithm's last step, a weight) in one kernel and not in another, and
+// the opacity cache written by the implicit step would differ in the last bit
+// from the one derived again from the stored state.
 template <typename R>
 __device__ __forceinline__ void table_coords(const OpacityParams &op, R rho, R T, R &lr, R &lt)
 {
+#pragma clang fp contract(off)
     lr = OMath<R>::log10_(rho) + R(op.lr_off);
     lt = OMath<R>::log10_(T) + R(op.lt_off);
     lr = lr < R(op.lr0) ? R(op.lr0) : (lr > R(op.lr1) ? R(op.lr1) : lr);
@@ -37,6 +43,7 @@ __device__ __forceinline__ void table_coords(const OpacityParams &op, R rho, R T
 template <typename R>
 __device__ __forceinline__ void table_lookup(const OpacityParams &op, R lr, R lt, R &lkP, R &lkR)
 {
+#pragma clang fp contract(off)
     const R u = (lr - R(op.lr0)) / (R(op.lr1) - R(op.lr0)) * R(op.nr - 1);
     const R v = (lt - R(op.lt0)) / (R(op.lt1) - R(op.lt0)) * R(op.nt - 1);
     int i = int(OMath<R>::floor_(u)), j = int(OMath<R>::floor_(v));

@@ -419,3 +419,27 @@ def test_injected_unrealizable_cells_are_fixed_like_the_oracle(orc, precision):
         # FP32 rounding can move a cell across the floor: counts within one
         assert all(abs(a - b) <= 1 for a, b in zip(diag["counters"][:3], cnt[:3])), (diag["counters"], cnt)
         assert_close_f32(got, ref, fp32_response(orc, p, 2, dt=dt), label="injected f32")
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_checkpoint_and_resume_is_bitwise(precision):
+    """Checkpoint / resume: the caller owns the state, so a checkpoint is a
+    copy of its arrays; a new context bound to the copy (the opacity cache
+    re-derived from the gas state) continues bit for bit like the context
+    that kept stepping (spherical grid, bilinear table: temperature-dependent
+    opacities)."""
+    from paper_2606_26268_amd import m1
+    p = I.make_c3(nr=24, nth=12, nph=20, dt=4.0e-5)
+    s = m1.Solver(p, precision)
+    s.step(p.dt, 3)
+    saved = s.state()
+    s.step(p.dt, 3)
+    a = s.state()
+    s.close()
+    q = I.Problem(**{**p.__dict__, "fields": saved})
+    r = m1.Solver(q, precision)
+    r.step(p.dt, 3)
+    b = r.state()
+    r.close()
+    for k in ALL:
+        assert np.array_equal(a[k], b[k]), k
