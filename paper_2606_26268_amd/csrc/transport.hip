@@ -472,7 +472,16 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
     auto zlin = [&](int kk, int c) { return map_index(kk, n2, bz0, bz1) * plane + c; };
     const R *wz = a.m.winv[2], *hpz = a.m.hp[2], *hmz = a.m.hm[2];
 
-    // register window of the thread's column: planes k-1 .. k+2, z slope of plane k
+    // register window of the thread's column: planes k-1 .. k+2, z slope of
+    // plane k.  Plane k+2 is loaded at the top of iteration k and first used
+    // after the x/y slopes (LATE): the neighbouring tiles read a plane's
+    // edge lines as their halo two planes after it was loaded, and those
+    // lines are still in L2.  Loaded a plane earlier (k+3 in iteration k),
+    // the halo read came three planes later and often missed: on the
+    // 192x96x192 grid the kernel fetched 136 MB per launch instead of
+    // 99 MB, and ran 1-2 % slower.  The general FP64 kernels, at the edge
+    // of the register file, keep the earlier load (the late one spills).
+    constexpr bool LATE = !(GENERAL && sizeof(R) == 8);
     R W[4][4], T1, T2, Fzlo[4], Fzhi[4], Sz0[4];
     Centre<R> C1;                       // f-fix quantities of plane k (W[1])
     {
@@ -481,15 +490,15 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
         load4(a, zlin(z0 - 1, col), W[0]);
         load4(a, zlin(z0, col), W[1]);
         load4(a, zlin(z0 + 1, col), W[2]);
-        load4(a, zlin(z0 + 2, col), W[3]);
+        if constexpr (!LATE) load4(a, zlin(z0 + 2, col), W[3]);
         fix_col(z0 - 2, Q0);
         fix_col(z0 - 1, W[0]);
         fix_col(z0, W[1]);
         fix_col(z0 + 1, W[2]);
-        fix_col(z0 + 2, W[3]);
+        if constexpr (!LATE) fix_col(z0 + 2, W[3]);
         const R Tm = a.tau[zlin(z0 - 1, col)];
         T1 = a.tau[zlin(z0, col)];
-        T2 = a.tau[zlin(z0 + 1, col)];
+        if constexpr (!LATE) T2 = a.tau[zlin(z0 + 1, col)];
         C1 = centre_of(W[1]);
         if constexpr (LIMO3) {
             // the face below plane z0 takes the upper-face slope of plane
@@ -526,11 +535,18 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
             else
                 __builtin_amdgcn_s_setprio(0);
         }
-        // prefetch the plane entering the window and this plane's halo
-        R Qn[4];
-        load4(a, zlin(k + 3, col), Qn);
-        fix_col(k + 3, Qn);
-        const R Tn = a.tau[zlin(k + 2, col)];
+        // the plane entering the window (LATE: k+2 now, else k+3 for the
+        // next iteration) and this plane's halo
+        R Qn[4], Tn = R(0);
+        if constexpr (LATE) {
+            load4(a, zlin(k + 2, col), W[3]);
+            fix_col(k + 2, W[3]);
+            T2 = a.tau[zlin(k + 1, col)];
+        } else {
+            load4(a, zlin(k + 3, col), Qn);
+            fix_col(k + 3, Qn);
+            Tn = a.tau[zlin(k + 2, col)];
+        }
         R Hq[4], Ht = R(0);
         if (tid < NHALO) {
             load4(a, k * plane + hcol, Hq);
@@ -628,10 +644,10 @@ __global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? 
             W[0][v] = W[1][v];
             W[1][v] = W[2][v];
             W[2][v] = W[3][v];
-            W[3][v] = Qn[v];
+            if constexpr (!LATE) W[3][v] = Qn[v];
         }
         T1 = T2;
-        T2 = Tn;
+        if constexpr (!LATE) T2 = Tn;
         C1 = C2;
     }
 }
