@@ -418,6 +418,12 @@ def form_table(I):
     def mg8():
         return I.make_multigroup(8, (128, 128, 128))
 
+    def limo3():
+        # LimO3 reconstruction (the general kernel's third-order limiter)
+        p3 = I.make_c3()
+        p3.limiter = 1
+        return p3
+
     def general():
         # the general transport kernel: Lax-Friedrichs flux with the simple
         # clip, reflective walls in x and irradiation heating
@@ -434,6 +440,7 @@ def form_table(I):
             # the second-order step (two split steps and the average)
             "c3_f32_table_rk2": (I.make_c3, "f32", True), "c1_mg8_f32_rk2": (mg8, "f32", True),
             "c1_f32_general": (general, "f32", False),
+            "c3_f32_limo3": (limo3, "f32", False), "c3_p64_limo3": (limo3, "p64", False),
             # the optically thin pulse the scheme's performance section times
             # (256^3, scattering only, second-order steps)
             "p0_pulse_f32_rk2": (I.make_pulse3d, "f32", True), "p0_pulse_p64_rk2": (I.make_pulse3d, "p64", True)}
