@@ -317,11 +317,16 @@ __device__ __forceinline__ int task_of(int p, int tid, int nx, int ny, int &dir)
 // 168 VGPRs: the general one just exceeds its bound otherwise, the default
 // one fits exactly.
 // LIMO3 (general kernel only): each donor cell keeps two slopes per
-// direction, one for its lower and one for its upper face; the extra
-// registers need a bound of two waves per SIMD in FP32 (three spilled) and
-// the 32 x 8 tile in FP64 (the 512-thread block spilled).
+// direction, one for its lower and one for its upper face, and takes the
+// 32 x 8 tile in FP64 (the 512-thread block spilled).  FP32 fits three
+// waves per SIMD.  FP64 asks for two waves per SIMD: the compiler then
+// keeps the kernel within 256 registers by spilling 14-22 of them to
+// scratch, and it runs 31 % faster than unbounded at 256 VGPRs plus
+// accumulation registers, one wave per SIMD (0.276 against 0.398 ms per
+// launch on the 192x96x192 grid).
 template <typename R, int GEOM, bool GENERAL, int TYB, bool LIMO3 = false>
-__global__ void __launch_bounds__((Tile<TYB>::NT), (sizeof(R) == 4 ? (GENERAL ? (LIMO3 ? 2 : 3) : 4) : 1))
+__global__ void __launch_bounds__((Tile<TYB>::NT),
+                                  (sizeof(R) == 4 ? (GENERAL ? 3 : 4) : (LIMO3 ? 2 : 1)))
     k_transport3d(TArgs<R> a, int nz_chunk, int tiles_x, int tiles_y, int nblocks, int cus)
 {
     using T = Tile<TYB>;
