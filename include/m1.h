@@ -349,7 +349,11 @@ m1_status m1_set_irradiation(m1_ctx *ctx, const double *q);
  * (the counters are cleared by a kernel, not a memset); calls that overlap
  * on one device (several streams or host threads) race on the shared array.
  * Asynchronous on the context's stream.  M1_ENOTSUP for multigroup
- * contexts, M1_ESTATE when a fixed boundary has no state. */
+ * contexts, M1_ESTATE when a fixed boundary has no state.  The library
+ * allocates nothing here; the FP64 LimO3 transport kernel keeps a few
+ * registers in per-lane scratch, whose backing the HIP runtime sets up at
+ * that kernel's first launch on a stream, so a caller that must not see
+ * even that runs one step before the allocation-free section. */
 #define M1_NOALLOC_MAX_BYTES (128u << 20)
 m1_status m1_step_noalloc(m1_ctx *ctx, const m1_fields *f, double dt);
 
