@@ -522,16 +522,17 @@ __global__ void __launch_bounds__((Tile<TYB>::NT),
         }
     }
 
-    // Default FP32 kernel: blocks b and b + cus share a compute unit (each
-    // XCD hands out its blocks in order, one per compute unit before the
+    // Default kernels: blocks b and b + cus share a compute unit (each XCD
+    // hands out its blocks in order, one per compute unit before the
     // second), and the wave arbiter favours the older block: left alone, the
     // first block on a unit finished its chunk in 70 % of the second's time
-    // (measured on the 192x96x192 grid), and the second then ran alone at
-    // half occupancy.  The two alternate their wave priority every plane and
-    // stay level (3-4 % faster transport with one round of blocks, 1 % with
-    // several).  FP64 blocks run one per unit and the general FP32 kernel
-    // three; for those the alternation did not pay (1-6 % slower).
-    constexpr bool ALTERNATE = sizeof(R) == 4 && !GENERAL;
+    // (FP32, measured on the 192x96x192 grid), and the second then ran alone
+    // at half occupancy.  The two alternate their wave priority every plane
+    // and stay level (FP32: 3-4 % faster transport with one round of blocks,
+    // 1 % with several; FP64, two 32 x 8 blocks per unit: 1-1.5 %).  The
+    // general kernels run other block counts per unit; for them the
+    // alternation did not pay (1-6 % slower).
+    constexpr bool ALTERNATE = !GENERAL;
     const int prio_grp = (int(blockIdx.x) / cus) & 1;
     for (int k = z0; k < z1; ++k) {
         if constexpr (ALTERNATE) {
@@ -723,14 +724,17 @@ static bool launch_tile(m1_ctx *c, const TArgs<R> &a, unsigned ngrp, long max_ro
     return true;
 }
 
-// The 32 x 16 tile where its launch takes at most two rounds of resident
-// blocks (the 192x96x192 and 128^3 grids: 1.5-3 % faster transport than
-// 32 x 8), else 32 x 8 (on the 256^3 grid and eight groups at 128^3,
-// launches of four to sixteen rounds, the taller blocks were 2-4 % slower).
+// Default FP32 kernel: the 32 x 16 tile where its launch takes at most two
+// rounds of resident blocks (the 192x96x192 and 128^3 grids: 1.5 % faster
+// transport than 32 x 8), else 32 x 8 (on the 256^3 grid and eight groups
+// at 128^3, launches of four to sixteen rounds, the taller blocks were
+// 2-4 % slower).  FP64 takes 32 x 8 everywhere: two of its blocks share a
+// compute unit and alternate priority (1-1.5 % faster than one 32 x 16
+// block per unit, which was 2 % faster than 32 x 8 without alternation).
 template <typename R, int GEOM, bool GENERAL, bool LIMO3 = false>
 static void launch_tiled(m1_ctx *c, const TArgs<R> &a, unsigned ngrp)
 {
-    if constexpr (!(sizeof(R) == 4 && GENERAL) && !LIMO3) {
+    if constexpr (sizeof(R) == 4 && !GENERAL && !LIMO3) {
         if (launch_tile<R, GEOM, GENERAL, 16, LIMO3>(c, a, ngrp, 2)) return;
     }
     launch_tile<R, GEOM, GENERAL, 8, LIMO3>(c, a, ngrp, 0);
