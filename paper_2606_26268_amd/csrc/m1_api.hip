@@ -2,6 +2,7 @@
 // validation, the separable grid metric, buffer ownership, the step state
 // machine and error reporting.  Kernels live in transport.hip, implicit.hip,
 // diag.hip and mlp.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -483,13 +484,30 @@ m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1
     if (nr < 2 || nt < 2 || !(lr1 > lr0) || !(lt1 > lt0) || sigma < 0)
         return fail(M1_EINVAL, "m1_set_opacity_table: need nr, nt >= 2, increasing axes, sigma >= 0");
     const size_t n = size_t(nr) * nt;
+    // device layout: the two tables as given, then (16-byte aligned) one
+    // record per table cell with its four node values of kappa_P and of
+    // kappa_R, so that a lookup reads two 16-byte words instead of
+    // gathering eight values from four rows
+    const size_t ncell = size_t(nr - 1) * (nt - 1), off = (2 * n + 3) & ~size_t(3);
+    std::vector<float> host(off + 8 * ncell, 0.0f);
+    std::copy(kP, kP + n, host.begin());
+    std::copy(kR, kR + n, host.begin() + n);
+    for (int j = 0; j + 1 < nt; ++j)
+        for (int i = 0; i + 1 < nr; ++i) {
+            const size_t o = size_t(j) * nr + i;
+            float *r = &host[off + 8 * (size_t(j) * (nr - 1) + i)];
+            const size_t node[4] = {o, o + 1, o + nr, o + nr + 1};
+            for (int q = 0; q < 4; ++q) {
+                r[q] = kP[node[q]];
+                r[4 + q] = kR[node[q]];
+            }
+        }
     // the new table is uploaded before the old one is released: on failure
     // the context keeps its previous opacity source unchanged
     float *tab = nullptr;
-    hipError_t e = device_alloc(reinterpret_cast<void **>(&tab), 2 * n * sizeof(float));
+    hipError_t e = device_alloc(reinterpret_cast<void **>(&tab), host.size() * sizeof(float));
     if (e != hipSuccess) return fail(M1_ENOMEM, "m1_set_opacity_table: allocation failed");
-    e = hipMemcpy(tab, kP, n * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(tab + n, kR, n * sizeof(float), hipMemcpyHostToDevice);
+    e = hipMemcpy(tab, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(tab);
         return hip_fail(e, "m1_set_opacity_table: upload");
@@ -509,6 +527,7 @@ m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1
     c->op.lt_off = lt_off;
     c->op.tab_kP = c->table_dev;
     c->op.tab_kR = c->table_dev + n;
+    c->op.tab_cells = c->table_dev + off;
     c->op.sigma = sigma;
     opacity_f32(c->op);
     return refresh(c);

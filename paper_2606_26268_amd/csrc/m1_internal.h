@@ -78,7 +78,11 @@ struct OpacityParams {
     int nr, nt;                                 // table
     double lr0, lr1, lt0, lt1, lr_off, lt_off;
     double lr_inv, lt_inv;                      // 1 / (lr1 - lr0), 1 / (lt1 - lt0)
-    const float *tab_kP, *tab_kR;               // device
+    const float *tab_kP, *tab_kR;               // device, [nt][nr] each
+    // device, per table cell (i, j) of [nt - 1][nr - 1]: kappa_P at its
+    // nodes (i, j), (i+1, j), (i, j+1), (i+1, j+1), then kappa_R likewise
+    // (two 16-byte words: one lookup reads 32 contiguous bytes)
+    const float *tab_cells;
     const float *mlp;                           // device, packed (see mlp.hip)
     double norm[4];
     // FP32 copies of the table axes and sigma for the network's FP32
@@ -165,7 +169,7 @@ struct m1_ctx {
 
     // opacity
     m1::OpacityParams op{};
-    float *table_dev = nullptr;            // [2][nt][nr]
+    float *table_dev = nullptr;            // [2][nt][nr], then the cell records
     float *mlp_dev = nullptr;              // packed network
     std::vector<float> mlp_theta;          // host copy of the float32 master
 };

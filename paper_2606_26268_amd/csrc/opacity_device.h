@@ -39,7 +39,8 @@ __device__ __forceinline__ void table_coords(const OpacityParams &op, R rho, R T
 }
 
 // Bilinear interpolation of log10 kappa_P and kappa_R at clamped (lr, lt);
-// both tables share the node grid, stored [2][nt][nr].
+// both tables share the node grid; the four node values of the cell come
+// from its record (see OpacityParams::tab_cells).
 template <typename R>
 __device__ __forceinline__ void table_lookup(const OpacityParams &op, R lr, R lt, R &lkP, R &lkR)
 {
@@ -50,12 +51,14 @@ __device__ __forceinline__ void table_lookup(const OpacityParams &op, R lr, R lt
     i = i > op.nr - 2 ? op.nr - 2 : (i < 0 ? 0 : i);
     j = j > op.nt - 2 ? op.nt - 2 : (j < 0 ? 0 : j);
     const R wu = u - R(i), wv = v - R(j);
-    const int o = j * op.nr + i;
-    const float *P = op.tab_kP, *Q = op.tab_kR;
+    // the cell's record: kappa_P, then kappa_R, at nodes (i, j), (i+1, j),
+    // (i, j+1), (i+1, j+1)
+    const float4 *rec = reinterpret_cast<const float4 *>(op.tab_cells) + 2 * (j * (op.nr - 1) + i);
+    const float4 P = rec[0], Q = rec[1];
     const R w00 = (R(1) - wu) * (R(1) - wv), w10 = wu * (R(1) - wv);
     const R w01 = (R(1) - wu) * wv, w11 = wu * wv;
-    lkP = w00 * R(P[o]) + w10 * R(P[o + 1]) + w01 * R(P[o + op.nr]) + w11 * R(P[o + op.nr + 1]);
-    lkR = w00 * R(Q[o]) + w10 * R(Q[o + 1]) + w01 * R(Q[o + op.nr]) + w11 * R(Q[o + op.nr + 1]);
+    lkP = w00 * R(P.x) + w10 * R(P.y) + w01 * R(P.z) + w11 * R(P.w);
+    lkR = w00 * R(Q.x) + w10 * R(Q.y) + w01 * R(Q.z) + w11 * R(Q.w);
 }
 
 // kappa_P, kappa_R of the analytic models and the table (OPK != MLP).
