@@ -93,17 +93,33 @@ __device__ __forceinline__ P &at(P *p, long base, unsigned t)
     return (p + base)[t];
 }
 
+// Read of element t of an input of the implicit step, which reads each
+// input once per step.  NT: with the nontemporal hint, which streams past
+// the caches (a probe of this kernel's read/write mix: 7.4 TB/s with it,
+// 5.9 without) and leaves the last-level cache to the step's outputs, which
+// the next transport reads; but inputs that are still in that cache (a
+// working set within a few hundred MB, fresh from the transport) are then
+// fetched from HBM again.  See NT_MIN_BYTES.
+template <bool NT, typename P>
+__device__ __forceinline__ P ld(const P *p, long base, unsigned t)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p + base + t);
+    else
+        return (p + base)[t];
+}
+
 // One cell of the implicit step (cell base + t of the block's run of cells);
-// returns the new gas temperature.  Four
+// returns the new gas temperature and, in rho, the cell's density.  Four
 // FP64 reciprocals per cell (hardware estimate refined by two Newton steps,
 // about 1 ulp): 1/rho, the determinant, the flux damping factor and the
 // optical depth per length.
-template <typename R, bool CONST_OPAC>
-__device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, unsigned t, R hmax)
+template <typename R, bool CONST_OPAC, bool NT>
+__device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, unsigned t, R hmax, double &rho)
 {
-    const double rho = at(a.rho, base, t);
-    double mx = at(a.gin[0], base, t), my = at(a.gin[1], base, t), mz = at(a.gin[2], base, t);
-    double Eg = at(a.gin[3], base, t);
+    rho = ld<NT>(a.rho, base, t);
+    double mx = ld<NT>(a.gin[0], base, t), my = ld<NT>(a.gin[1], base, t), mz = ld<NT>(a.gin[2], base, t);
+    double Eg = ld<NT>(a.gin[3], base, t);
     const double inv_rho = Num<double>::rcp(rho);
     const double Cv = rho * a.k.inv_gm1;
     const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
@@ -112,11 +128,11 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, un
         rkP = rho * a.op.kP;
         rchi = rho * (a.op.kR + a.op.sigma);
     } else {
-        rkP = double(at(a.rkp, base, t));
-        rchi = double(at(a.tau, base, t)) * Num<double>::rcp(double(hmax));
+        rkP = double(ld<NT>(a.rkp, base, t));
+        rchi = double(ld<NT>(a.tau, base, t)) * Num<double>::rcp(double(hmax));
     }
-    const double Es = double(at(a.Es, base, t));
-    const double Fs[3] = {double(at(a.Fxs, base, t)), double(at(a.Fys, base, t)), double(at(a.Fzs, base, t))};
+    const double Es = double(ld<NT>(a.Es, base, t));
+    const double Fs[3] = {double(ld<NT>(a.Fxs, base, t)), double(ld<NT>(a.Fys, base, t)), double(ld<NT>(a.Fzs, base, t))};
     // Eq. implicit_matrix with gamma_abs,red = dt c_hat kappa_P rho and
     // gamma_abs = dt c kappa_P rho, inverted by Cramer's rule in a
     // cancellation-free arrangement (det > 0)
@@ -126,7 +142,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, un
     const double det = Cv * (1.0 + gr) + 4.0 * g * aT3;
     // irradiation energy deposited in the step enters the S_1 row (Sect. 2.9)
     double S = 0.0;
-    if (a.irr) S = at(a.irr, base, t) * a.k.dt;
+    if (a.irr) S = ld<NT>(a.irr, base, t) * a.k.dt;
     // uniform branch: the absorption-only form costs the default path nothing
     double E1;
     if (a.absorb)
@@ -154,12 +170,12 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, un
     if (a.ravg[0]) {
         // second-order step: U^{n+1} = (U^n + U2) / 2 (the averaging partner
         // is read before this cell is written)
-        E1r = R(0.5 * (double(at(a.ravg[0], base, t)) + double(E1r)));
-        for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(at(a.ravg[1 + v], base, t)) + double(F1r[v])));
-        mx = 0.5 * (at(a.gavg[0], base, t) + mx);
-        my = 0.5 * (at(a.gavg[1], base, t) + my);
-        mz = 0.5 * (at(a.gavg[2], base, t) + mz);
-        Eg = 0.5 * (at(a.gavg[3], base, t) + Eg);
+        E1r = R(0.5 * (double(ld<NT>(a.ravg[0], base, t)) + double(E1r)));
+        for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(ld<NT>(a.ravg[1 + v], base, t)) + double(F1r[v])));
+        mx = 0.5 * (ld<NT>(a.gavg[0], base, t) + mx);
+        my = 0.5 * (ld<NT>(a.gavg[1], base, t) + my);
+        mz = 0.5 * (ld<NT>(a.gavg[2], base, t) + mz);
+        Eg = 0.5 * (ld<NT>(a.gavg[3], base, t) + Eg);
     }
     at(a.E, base, t) = E1r;
     at(a.Fx, base, t) = F1r[0];
@@ -172,7 +188,7 @@ __device__ __forceinline__ double implicit_cell(const IArgs<R> &a, long base, un
     return gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
 }
 
-template <typename R, int OPK>
+template <typename R, int OPK, bool NT>
 __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
 {
     const int n0 = a.n[0], n1 = a.n[1];
@@ -185,9 +201,10 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
     a.ix.split(id, i, j, k);
     // the cell extent serves both the optical depth read and the one written
     const R hm = OPK == OPK_CONST ? R(0) : cell_hmax(a.m, a.ndim, i, j, k);
-    const double T1 = implicit_cell<R, OPK == OPK_CONST>(a, base, t, hm);
+    double rho_d;
+    const double T1 = implicit_cell<R, OPK == OPK_CONST, NT>(a, base, t, hm, rho_d);
     if (OPK != OPK_CONST) {
-        const R rho = R(at(a.rho, base, t));
+        const R rho = R(rho_d);
         R kP, kR;
         opacity_analytic<R, OPK>(a.op, rho, R(T1), kP, kR);
         cache_entry(rho, kP, kR, R(a.op.sigma), hm, at(a.rkp, base, t), at(a.tau, base, t));
@@ -200,7 +217,7 @@ __global__ void __launch_bounds__(256) k_implicit(IArgs<R> a)
 // before the weights are staged into LDS: its many array pointers are then
 // dead during the staging, which keeps the kernel within the scalar register
 // file (staged first, the pointers were spilled to vector lanes).
-template <typename R>
+template <typename R, bool NT>
 __global__ void __launch_bounds__(256, 4) k_implicit_mlp(IArgs<R> a)
 {
     const int n0 = a.n[0], n1 = a.n[1];
@@ -216,9 +233,10 @@ __global__ void __launch_bounds__(256, 4) k_implicit_mlp(IArgs<R> a)
         int i, j, k;
         a.ix.split(idc, i, j, k);
         const R hm = cell_hmax(a.m, a.ndim, i, j, k);
-        double T1 = 1.0;
-        if (live) T1 = implicit_cell<R, false>(a, base, t, hm);
-        const float rho = float(a.rho[idc]);
+        // lanes past the last cell evaluate the network at rho = T = 1
+        double T1 = 1.0, rho_d = 1.0;
+        if (live) T1 = implicit_cell<R, false, NT>(a, base, t, hm, rho_d);
+        const float rho = float(rho_d);
         mlp_stage(a.op.mlp, sh, threadIdx.x, blockDim.x);
         __syncthreads();
         float kP, kR;
@@ -317,6 +335,17 @@ static void rk2_stage_args(m1_ctx *c, IArgs<R> &a, int stage)
     }
 }
 
+// Streaming reads in the implicit step above this many bytes per step.
+// Measured on one box (A/B of both forms, 100-step runs): on the 256^3 box
+// and the 192x96x192 grid in FP64 the hint made the whole step 1.6 % and
+// 5.5 % faster (the next transport then finds the step's outputs in the
+// 256 MB last-level cache), and the network form's 2 %; on the 128^3 box
+// (285 MB FP64, 220 MB FP32) the inputs were still cached and the implicit
+// kernel took 18-25 % longer with it.  The FP32 table form at 192x96x192
+// (425 MB) came out 1 % slower, the one measured case above the line
+// that did not gain.
+constexpr double NT_MIN_BYTES = 384.0 * (1 << 20);
+
 template <typename R>
 static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met, int stage = 0)
 {
@@ -325,13 +354,23 @@ static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met, int stage
     rk2_stage_args(c, a, stage);
     const int N = c->n[0] * c->n[1] * c->n[2];
     dim3 block(256), grid((N + 255) / 256);
-    switch (c->op.kind) {
-    case OPK_CONST: hipLaunchKernelGGL((k_implicit<R, OPK_CONST>), grid, block, 0, c->stream, a); break;
-    case OPK_POWERLAW: hipLaunchKernelGGL((k_implicit<R, OPK_POWERLAW>), grid, block, 0, c->stream, a); break;
-    case OPK_TABLE: hipLaunchKernelGGL((k_implicit<R, OPK_TABLE>), grid, block, 0, c->stream, a); break;
-    default:
-        hipLaunchKernelGGL((k_implicit_mlp<R>), grid, block, 0, c->stream, a);
-        break;
+    // the step's bytes: E*, F* in, E, F out, the gas in and out, the
+    // opacity cache in and out
+    const double bytes = double(N) * (8.0 * sizeof(R) + 72.0 + (c->op.kind == OPK_CONST ? 0.0 : 4.0 * sizeof(R)));
+    if (bytes >= NT_MIN_BYTES) {
+        switch (c->op.kind) {
+        case OPK_CONST: hipLaunchKernelGGL((k_implicit<R, OPK_CONST, true>), grid, block, 0, c->stream, a); break;
+        case OPK_POWERLAW: hipLaunchKernelGGL((k_implicit<R, OPK_POWERLAW, true>), grid, block, 0, c->stream, a); break;
+        case OPK_TABLE: hipLaunchKernelGGL((k_implicit<R, OPK_TABLE, true>), grid, block, 0, c->stream, a); break;
+        default: hipLaunchKernelGGL((k_implicit_mlp<R, true>), grid, block, 0, c->stream, a); break;
+        }
+    } else {
+        switch (c->op.kind) {
+        case OPK_CONST: hipLaunchKernelGGL((k_implicit<R, OPK_CONST, false>), grid, block, 0, c->stream, a); break;
+        case OPK_POWERLAW: hipLaunchKernelGGL((k_implicit<R, OPK_POWERLAW, false>), grid, block, 0, c->stream, a); break;
+        case OPK_TABLE: hipLaunchKernelGGL((k_implicit<R, OPK_TABLE, false>), grid, block, 0, c->stream, a); break;
+        default: hipLaunchKernelGGL((k_implicit_mlp<R, false>), grid, block, 0, c->stream, a); break;
+        }
     }
     return hipGetLastError();
 }

@@ -48,7 +48,8 @@ def test_default_kernels_keep_their_occupancy(res):
     fp32_default = [k for k in res if k.startswith("_ZN2m113k_transport3dIfLi")
                     and k.split("ELi")[0].endswith("ELb0") and "ELb0EE" in k.split("ELi")[1]]
     assert len(fp32_default) == 6, fp32_default
+    # k_implicit_mlp<R, NT>: both precisions, with and without streaming reads
     mlp = [k for k in res if k.startswith("_ZN2m114k_implicit_mlp")]
-    assert len(mlp) == 2, mlp
+    assert len(mlp) == 4, mlp
     for k in fp32_default + mlp:
         assert res[k]["waves_per_simd"] >= 4, (k, res[k])
