@@ -343,7 +343,8 @@ static void rk2_stage_args(m1_ctx *c, IArgs<R> &a, int stage)
 // (285 MB FP64, 220 MB FP32) the inputs were still cached and the implicit
 // kernel took 18-25 % longer with it.  The FP32 table form at 192x96x192
 // (425 MB) came out 1 % slower, the one measured case above the line
-// that did not gain.
+// that did not gain.  The multigroup kernel follows the same rule (eight
+// groups at 128^3: its launch 6-9 % faster, the step 1.3-1.4 %).
 constexpr double NT_MIN_BYTES = 384.0 * (1 << 20);
 
 template <typename R>
@@ -453,18 +454,19 @@ __global__ void __launch_bounds__(256) k_tau_mg(IArgs<R> a, MgArgs<R> g, unsigne
 //   L  = a (4 T^3 T' - 3 T^4) = a T^3 (C_v T + 4 S + 4 sum_g g_g E*_g / (1 + gr_g)) / D,
 //   E'_g = (E*_g + gr_g b_g L) / (1 + gr_g),
 // O(m) work and no cancellation.
-template <typename R, int MG>
+template <typename R, int MG, bool NT>
 __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
 {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= g.N) return;
     const int m = g.gp.m;
-    const double rho = a.rho[id];
-    double mx = a.gin[0][id], my = a.gin[1][id], mz = a.gin[2][id], Eg = a.gin[3][id];
+    const double rho = ld<NT>(a.rho, 0, id);
+    double mx = ld<NT>(a.gin[0], 0, id), my = ld<NT>(a.gin[1], 0, id), mz = ld<NT>(a.gin[2], 0, id);
+    double Eg = ld<NT>(a.gin[3], 0, id);
     const double inv_rho = Num<double>::rcp(rho);
     const double Cv = rho * a.k.inv_gm1;
     const double T = gas_T_r(inv_rho, mx, my, mz, Eg, a.k.gm1);
-    const double S = a.irr ? a.irr[id] * a.k.dt : 0.0;
+    const double S = a.irr ? ld<NT>(a.irr, 0, id) * a.k.dt : 0.0;
     const double aT3 = a.k.a * T * T * T;
     const double iT = Num<double>::rcp(T);
     // pass 1: group fractions, transported energies and the reduced equation
@@ -477,7 +479,7 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
             const double hi = q + 1 < m ? planck_fraction(g.gp.edges[q] * iT) : 1.0;
             b[q] = hi - lo;
             lo = hi;
-            Es[q] = double(reinterpret_cast<const R *>(g.star + 4 * q * g.plane)[id]);
+            Es[q] = double(ld<NT>(reinterpret_cast<const R *>(g.star + 4 * q * g.plane), 0, id));
             const double kr = rho * g.gp.kP[q];
             inv1[q] = Num<double>::rcp(1.0 + a.k.dt_ch * kr);
             const double gg = a.k.dt_c * kr;
@@ -496,7 +498,7 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
             const double inv_damp = Num<double>::rcp(1.0 + a.k.dt_ch * rho * (g.gp.kR[q] + g.gp.sigma));
             double F1[3], Fs[3];
             for (int v = 0; v < 3; ++v) {
-                Fs[v] = double(reinterpret_cast<const R *>(g.star + (4 * q + 1 + v) * g.plane)[id]);
+                Fs[v] = double(ld<NT>(reinterpret_cast<const R *>(g.star + (4 * q + 1 + v) * g.plane), 0, id));
                 F1[v] = Fs[v] * inv_damp;
             }
             const double Fn = Num<double>::sqrt_(F1[0] * F1[0] + F1[1] * F1[1] + F1[2] * F1[2]);
@@ -515,8 +517,8 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
             if (a.ravg[0]) {
                 // second-order step: (U^n + U2) / 2, the partner read before
                 // this cell is written
-                E1r = R(0.5 * (double(a.ravg[0][o]) + double(E1r)));
-                for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(a.ravg[1 + v][o]) + double(F1r[v])));
+                E1r = R(0.5 * (double(ld<NT>(a.ravg[0], o, 0)) + double(E1r)));
+                for (int v = 0; v < 3; ++v) F1r[v] = R(0.5 * (double(ld<NT>(a.ravg[1 + v], o, 0)) + double(F1r[v])));
             }
             a.E[o] = E1r;
             a.Fx[o] = F1r[0];
@@ -529,10 +531,10 @@ __global__ void __launch_bounds__(256) k_implicit_mg(IArgs<R> a, MgArgs<R> g)
     my -= dF[1] * a.k.inv_ch;
     mz -= dF[2] * a.k.inv_ch;
     if (a.ravg[0]) {
-        mx = 0.5 * (a.gavg[0][id] + mx);
-        my = 0.5 * (a.gavg[1][id] + my);
-        mz = 0.5 * (a.gavg[2][id] + mz);
-        Eg = 0.5 * (a.gavg[3][id] + Eg);
+        mx = 0.5 * (ld<NT>(a.gavg[0], 0, id) + mx);
+        my = 0.5 * (ld<NT>(a.gavg[1], 0, id) + my);
+        mz = 0.5 * (ld<NT>(a.gavg[2], 0, id) + mz);
+        Eg = 0.5 * (ld<NT>(a.gavg[3], 0, id) + Eg);
     }
     a.Eg[id] = Eg;
     a.mx[id] = mx;
@@ -551,6 +553,19 @@ static MgArgs<R> mg_args(m1_ctx *c)
     return g;
 }
 
+template <typename R, bool NT>
+static void launch_mg_kernel(m1_ctx *c, dim3 grid, dim3 block, const IArgs<R> &a, const MgArgs<R> &g)
+{
+    if (g.gp.m <= 4)
+        hipLaunchKernelGGL((k_implicit_mg<R, 4, NT>), grid, block, 0, c->stream, a, g);
+    else if (g.gp.m <= 8)
+        hipLaunchKernelGGL((k_implicit_mg<R, 8, NT>), grid, block, 0, c->stream, a, g);
+    else if (g.gp.m <= 16)
+        hipLaunchKernelGGL((k_implicit_mg<R, 16, NT>), grid, block, 0, c->stream, a, g);
+    else
+        hipLaunchKernelGGL((k_implicit_mg<R, 32, NT>), grid, block, 0, c->stream, a, g);
+}
+
 template <typename R>
 static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met, int stage = 0)
 {
@@ -559,14 +574,11 @@ static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met, int st
     rk2_stage_args(c, a, stage);
     const MgArgs<R> g = mg_args<R>(c);
     const dim3 grid(unsigned((g.N + 255) / 256)), block(256);
-    if (g.gp.m <= 4)
-        hipLaunchKernelGGL((k_implicit_mg<R, 4>), grid, block, 0, c->stream, a, g);
-    else if (g.gp.m <= 8)
-        hipLaunchKernelGGL((k_implicit_mg<R, 8>), grid, block, 0, c->stream, a, g);
-    else if (g.gp.m <= 16)
-        hipLaunchKernelGGL((k_implicit_mg<R, 16>), grid, block, 0, c->stream, a, g);
+    const double bytes = double(g.N) * (8.0 * sizeof(R) * g.gp.m + 72.0);
+    if (bytes >= NT_MIN_BYTES)
+        launch_mg_kernel<R, true>(c, grid, block, a, g);
     else
-        hipLaunchKernelGGL((k_implicit_mg<R, 32>), grid, block, 0, c->stream, a, g);
+        launch_mg_kernel<R, false>(c, grid, block, a, g);
     return hipGetLastError();
 }
 
