@@ -108,7 +108,15 @@ typedef struct {
  *         phi = max(0, min(p3, max(-theta/2, min(2 theta, p3, 3/2)))),
  *         p3 = (2 + theta)/3, the face value u + phi (face-side divided
  *         difference) (x_face - x_cell); each face of a cell has its own
- *         slope.  The face treatment (recon) applies to either. */
+ *         slope.  The face treatment (recon) applies to either.
+ * stream_reads  how the implicit step reads its inputs (each once per
+ *         step): M1_STREAM_AUTO (default) with a nontemporal hint, which
+ *         streams them past the caches and leaves the last-level cache to
+ *         the step's outputs, when a step moves at least 384 MiB, else as
+ *         plain loads; M1_STREAM_ON always; M1_STREAM_OFF never.  Results are
+ *         bit-identical; only the speed differs (execution tuning, no
+ *         passage of the paper). */
+typedef enum { M1_STREAM_AUTO = 0, M1_STREAM_ON = 1, M1_STREAM_OFF = 2 } m1_stream_reads;
 typedef struct {
     double c;
     double a_rad;
@@ -120,6 +128,7 @@ typedef struct {
     int absorb_only;
     int second_order;
     int limiter;
+    int stream_reads;
 } m1_params;
 
 /* Caller-owned device state bound to a context (see conventions). */

@@ -347,6 +347,14 @@ static void rk2_stage_args(m1_ctx *c, IArgs<R> &a, int stage)
 // groups at 128^3: its launch 6-9 % faster, the step 1.3-1.4 %).
 constexpr double NT_MIN_BYTES = 384.0 * (1 << 20);
 
+// whether the implicit step of a context streams its reads (m1_params.stream_reads)
+static bool stream_reads(const m1_ctx *c, double bytes)
+{
+    if (c->par.stream_reads == M1_STREAM_ON) return true;
+    if (c->par.stream_reads == M1_STREAM_OFF) return false;
+    return bytes >= NT_MIN_BYTES;
+}
+
 template <typename R>
 static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met, int stage = 0)
 {
@@ -358,7 +366,7 @@ static hipError_t launch_i(m1_ctx *c, double dt, const Metric<R> &met, int stage
     // the step's bytes: E*, F* in, E, F out, the gas in and out, the
     // opacity cache in and out
     const double bytes = double(N) * (8.0 * sizeof(R) + 72.0 + (c->op.kind == OPK_CONST ? 0.0 : 4.0 * sizeof(R)));
-    if (bytes >= NT_MIN_BYTES) {
+    if (stream_reads(c, bytes)) {
         switch (c->op.kind) {
         case OPK_CONST: hipLaunchKernelGGL((k_implicit<R, OPK_CONST, true>), grid, block, 0, c->stream, a); break;
         case OPK_POWERLAW: hipLaunchKernelGGL((k_implicit<R, OPK_POWERLAW, true>), grid, block, 0, c->stream, a); break;
@@ -575,7 +583,7 @@ static hipError_t launch_i_mg(m1_ctx *c, double dt, const Metric<R> &met, int st
     const MgArgs<R> g = mg_args<R>(c);
     const dim3 grid(unsigned((g.N + 255) / 256)), block(256);
     const double bytes = double(g.N) * (8.0 * sizeof(R) * g.gp.m + 72.0);
-    if (bytes >= NT_MIN_BYTES)
+    if (stream_reads(c, bytes))
         launch_mg_kernel<R, true>(c, grid, block, a, g);
     else
         launch_mg_kernel<R, false>(c, grid, block, a, g);

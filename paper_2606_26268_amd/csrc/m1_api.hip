@@ -285,6 +285,7 @@ m1_status m1_params_default(double c_hat, m1_params *p)
     p->absorb_only = 0;
     p->second_order = 0;
     p->limiter = M1_LIMITER_PLM;
+    p->stream_reads = M1_STREAM_AUTO;
     return M1_OK;
 }
 
@@ -333,6 +334,8 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
         return fail(M1_EINVAL, "m1_create: second_order must be 0 or 1");
     if (par.limiter != M1_LIMITER_PLM && par.limiter != M1_LIMITER_LIMO3)
         return fail(M1_EINVAL, "m1_create: unknown limiter");
+    if (par.stream_reads < M1_STREAM_AUTO || par.stream_reads > M1_STREAM_OFF)
+        return fail(M1_EINVAL, "m1_create: unknown stream_reads mode");
     if (!(par.c > 0.0) || !(par.gamma > 1.0) || !(par.a_rad > 0.0))
         return fail(M1_EINVAL, "m1_create: c, a_rad must be > 0 and gamma > 1");
     m1_ctx *c = new (std::nothrow) m1_ctx();

@@ -27,6 +27,7 @@ M1_OPAC_CONSTANT, M1_OPAC_POWERLAW = 0, 1
 M1_RECON_FPRESERVE, M1_RECON_PLUTO, M1_RECON_CLIP = 0, 1, 2
 M1_RIEMANN_HLL, M1_RIEMANN_LF = 0, 1
 M1_LIMITER_PLM, M1_LIMITER_LIMO3 = 0, 1
+M1_STREAM_AUTO, M1_STREAM_ON, M1_STREAM_OFF = 0, 1, 2
 M1_MLP_NPARAM = 4486
 
 
@@ -45,7 +46,7 @@ class m1_params(C.Structure):
     _fields_ = [("c", C.c_double), ("a_rad", C.c_double), ("gamma", C.c_double),
                 ("precision", C.c_int), ("e_floor", C.c_double), ("recon", C.c_int), ("riemann", C.c_int),
                 ("absorb_only", C.c_int),
-                ("second_order", C.c_int), ("limiter", C.c_int)]
+                ("second_order", C.c_int), ("limiter", C.c_int), ("stream_reads", C.c_int)]
 
 
 class m1_fields(C.Structure):
@@ -356,6 +357,7 @@ class Solver:
         par.absorb_only = int(getattr(prob, "absorb_only", 0))
         par.second_order = int(bool(second_order))
         par.limiter = int(getattr(prob, "limiter", 0))
+        par.stream_reads = int(getattr(prob, "stream_reads", 0))
         self.ctx = m1_create(prob.ndim, prob.n, prob.faces, prob.bc, prob.geometry, prob.c_hat, par)
         bs = getattr(prob, "bc_state", None)
         if bs is not None:

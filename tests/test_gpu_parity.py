@@ -443,3 +443,37 @@ def test_checkpoint_and_resume_is_bitwise(precision):
     r.close()
     for k in ALL:
         assert np.array_equal(a[k], b[k]), k
+
+
+def _mlp_weights():
+    th = I.mlp_init(7)
+    rng = np.random.default_rng(7)
+    tab = I.make_table()
+    a, b = tab["log10_kP"].astype(np.float64), tab["log10_kR"].astype(np.float64)
+    return dict(theta=(th + 0.05 * rng.normal(size=th.size)).astype(np.float32),
+                norm=np.array([a.mean(), a.std(), b.mean(), b.std()]))
+
+
+@pytest.mark.parametrize("precision", ["p64", "f32"])
+def test_streaming_reads_change_no_bit(precision):
+    """The implicit step's two ways of reading its inputs (m1_params.
+    stream_reads: nontemporal loads, or plain ones) give the same bits, for
+    the table, the network, the second-order step and eight groups; the
+    automatic choice takes one of them by the step's size, so both kernels
+    of each form are checked here on small grids."""
+    from paper_2606_26268_amd import m1
+    cases = [("table", I.make_c3(nr=24, nth=12, nph=20, dt=4.0e-5), None, False),
+             ("table rk2", I.make_c3(nr=24, nth=12, nph=20, dt=4.0e-5), None, True),
+             ("network", I.make_c4(nr=24, nth=12, nph=20, dt=4.0e-5), _mlp_weights(), False),
+             ("groups", I.make_multigroup(8, (16, 16, 16)), None, False)]
+    for name, p, mlp, rk2 in cases:
+        say(f"case stream_reads {name} {precision}")
+        out = []
+        for mode in (m1.M1_STREAM_ON, m1.M1_STREAM_OFF):
+            p.stream_reads = mode
+            s = m1.Solver(p, precision, mlp=mlp, second_order=rk2)
+            s.step(p.dt, 3, rk2=rk2)
+            out.append(s.state())
+            s.close()
+        for k in out[0]:
+            assert np.array_equal(out[0][k], out[1][k]), (name, k)

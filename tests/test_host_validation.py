@@ -75,7 +75,7 @@ def test_create_rejects_too_many_cells():
 
 
 PARAM_CASES = [("precision", 7, "precision"), ("recon", 3, "reconstruction"), ("riemann", 2, "Riemann"),
-               ("absorb_only", 2, "absorb_only"), ("second_order", -1, "second_order"), ("limiter", 2, "limiter"),
+               ("absorb_only", 2, "absorb_only"), ("second_order", -1, "second_order"), ("limiter", 2, "limiter"), ("stream_reads", 3, "stream_reads"),
                ("c", 0.0, "gamma"), ("gamma", 1.0, "gamma"), ("a_rad", -1.0, "gamma")]
 
 
