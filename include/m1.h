@@ -243,6 +243,9 @@ m1_status m1_set_opacity_model(m1_ctx *ctx, int kind, const double *params);
  * include both axis ends: node (i, j) at (lr_min + i h_r, lt_min + j h_t),
  * host float32 arrays [nt][nr] (copied).  Looked up at
  * (log10 rho + lr_off, log10 T + lt_off), clamped to the axes.  nr, nt >= 2.
+ * The library keeps the tables and, for the lookup, one 32-byte record per
+ * table cell with its four node values of both (device memory of about
+ * 40 nr nt bytes, and as much host memory while the call runs).
  * On M1_ENOMEM or an upload error the previous opacity source is kept. */
 m1_status m1_set_opacity_table(m1_ctx *ctx, int nr, int nt, double lr_min, double lr_max,
                                double lt_min, double lt_max, double lr_off, double lt_off,
