@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,16 @@ static m1_status fail(m1_status s, const std::string &msg)
 {
     set_error(msg);
     return s;
+}
+
+// The C interface lets no exception through: a host allocation that fails
+// inside the library (std::bad_alloc, or std::length_error for an absurd
+// size) makes the call return M1_ENOMEM, with a message that itself
+// allocates nothing.
+static m1_status host_oom(const char *msg)
+{
+    set_error(msg);
+    return M1_ENOMEM;
 }
 
 static m1_status hip_fail(hipError_t e, const char *what)
@@ -289,7 +300,7 @@ m1_status m1_params_default(double c_hat, m1_params *p)
     return M1_OK;
 }
 
-m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_params *p, m1_ctx **out)
+m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_params *p, m1_ctx **out) try
 {
     if (!g || !out) return fail(M1_EINVAL, "m1_create: NULL argument");
     *out = nullptr;
@@ -340,31 +351,38 @@ m1_status m1_create(const m1_grid *g, m1_geometry geom, double c_hat, const m1_p
         return fail(M1_EINVAL, "m1_create: c, a_rad must be > 0 and gamma > 1");
     m1_ctx *c = new (std::nothrow) m1_ctx();
     if (!c) return fail(M1_ENOMEM, "m1_create: host allocation failed");
-    c->ndim = g->ndim;
-    c->geom = geom;
-    c->c_hat = c_hat;
-    c->par = par;
-    for (int d = 0; d < 3; ++d) {
-        c->n[d] = g->n[d];
-        c->bc[d][0] = g->bc[d][0];
-        c->bc[d][1] = g->bc[d][1];
-        c->faces[d].assign(g->faces[d], g->faces[d] + g->n[d] + 1);
-    }
-    hipGetDevice(&c->device);
-    int cu = 0;
-    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0)
-        c->cus = cu;
-    noalloc_setup(c->device);
-    c->op.kind = OPK_CONST;
-    HostMetric M;
-    build_metric(c, M);
-    m1_status s = upload_metric(c, M);
-    if (s != M1_OK) {
-        m1_destroy(c);
-        return s;
+    try {
+        c->ndim = g->ndim;
+        c->geom = geom;
+        c->c_hat = c_hat;
+        c->par = par;
+        for (int d = 0; d < 3; ++d) {
+            c->n[d] = g->n[d];
+            c->bc[d][0] = g->bc[d][0];
+            c->bc[d][1] = g->bc[d][1];
+            c->faces[d].assign(g->faces[d], g->faces[d] + g->n[d] + 1);
+        }
+        hipGetDevice(&c->device);
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0)
+            c->cus = cu;
+        noalloc_setup(c->device);
+        c->op.kind = OPK_CONST;
+        HostMetric M;
+        build_metric(c, M);
+        m1_status s = upload_metric(c, M);
+        if (s != M1_OK) {
+            m1_destroy(c);
+            return s;
+        }
+    } catch (const std::exception &) {
+        m1_destroy(c);        // the partly built context goes with the error
+        return host_oom("m1_create: host allocation failed");
     }
     *out = c;
     return M1_OK;
+} catch (const std::exception &) {
+    return host_oom("m1_create: host allocation failed");
 }
 
 m1_status m1_destroy(m1_ctx *c)
@@ -388,7 +406,7 @@ m1_status m1_set_stream(m1_ctx *c, void *stream)
 
 static bool aligned(const void *p) { return p && (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
-m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
+m1_status m1_bind_state(m1_ctx *c, const m1_fields *f) try
 {
     if (!c || !f) return fail(M1_EINVAL, "m1_bind_state: NULL argument");
     const void *ptrs[9] = {f->E, f->Fx, f->Fy, f->Fz, f->rho, f->mx, f->my, f->mz, f->Eg};
@@ -444,6 +462,8 @@ m1_status m1_bind_state(m1_ctx *c, const m1_fields *f)
         return hip_fail(e, "m1_bind_state: counter reset / opacity cache");
     }
     return M1_OK;
+} catch (const std::exception &) {
+    return host_oom("m1_bind_state: host allocation failed");
 }
 
 static m1_status refresh(m1_ctx *c)
@@ -481,7 +501,7 @@ m1_status m1_set_opacity_model(m1_ctx *c, int kind, const double *p)
 }
 
 m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1, double lt0, double lt1,
-                               double lr_off, double lt_off, const float *kP, const float *kR, double sigma)
+                               double lr_off, double lt_off, const float *kP, const float *kR, double sigma) try
 {
     if (!c || !kP || !kR) return fail(M1_EINVAL, "m1_set_opacity_table: NULL argument");
     if (nr < 2 || nt < 2 || !(lr1 > lr0) || !(lt1 > lt0) || sigma < 0)
@@ -534,9 +554,11 @@ m1_status m1_set_opacity_table(m1_ctx *c, int nr, int nt, double lr0, double lr1
     c->op.sigma = sigma;
     opacity_f32(c->op);
     return refresh(c);
+} catch (const std::exception &) {
+    return host_oom("m1_set_opacity_table: host allocation failed");
 }
 
-m1_status m1_set_opacity_mlp(m1_ctx *c, const m1_mlp *w)
+m1_status m1_set_opacity_mlp(m1_ctx *c, const m1_mlp *w) try
 {
     if (!c || !w || !w->theta) return fail(M1_EINVAL, "m1_set_opacity_mlp: NULL argument");
     if (!c->table_dev) return fail(M1_ESTATE, "m1_set_opacity_mlp: set the table first (input axes)");
@@ -544,9 +566,11 @@ m1_status m1_set_opacity_mlp(m1_ctx *c, const m1_mlp *w)
     if (mlp_pack(c, w->theta, w->norm) != 0) return M1_EDEVICE;
     c->op.kind = OPK_MLP;
     return refresh(c);
+} catch (const std::exception &) {
+    return host_oom("m1_set_opacity_mlp: host allocation failed");
 }
 
-m1_status m1_mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
+m1_status m1_mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep) try
 {
     if (!c || !cfg || !rep || !cfg->samples || !cfg->theta_init)
         return fail(M1_EINVAL, "m1_mlp_train: NULL argument");
@@ -559,19 +583,23 @@ m1_status m1_mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
     if (r != 0) return r < 0 ? m1_status(r) : M1_EDEVICE;
     c->op.kind = OPK_MLP;
     return refresh(c);
+} catch (const std::exception &) {
+    return host_oom("m1_mlp_train: host allocation failed");
 }
 
-m1_status m1_mlp_get(m1_ctx *c, float *theta, double *norm)
+m1_status m1_mlp_get(m1_ctx *c, float *theta, double *norm) try
 {
     if (!c || !theta || !norm) return fail(M1_EINVAL, "m1_mlp_get: NULL argument");
     if (c->mlp_theta.size() != M1_MLP_NPARAM) return fail(M1_ESTATE, "m1_mlp_get: no network set");
     std::memcpy(theta, c->mlp_theta.data(), M1_MLP_NPARAM * sizeof(float));
     for (int i = 0; i < 4; ++i) norm[i] = c->op.norm[i];
     return M1_OK;
+} catch (const std::exception &) {
+    return host_oom("m1_mlp_get: host allocation failed");
 }
 
 m1_status m1_mlp_gradient(m1_ctx *c, const float *samples, long n, const float *theta, float *grad,
-                          double *loss)
+                          double *loss) try
 {
     if (!c || !samples || !theta || !grad || !loss) return fail(M1_EINVAL, "m1_mlp_gradient: NULL argument");
     if (n < 64 || n % 64) return fail(M1_EINVAL, "m1_mlp_gradient: n must be a positive multiple of 64");
@@ -580,6 +608,8 @@ m1_status m1_mlp_gradient(m1_ctx *c, const float *samples, long n, const float *
     int r = mlp_gradient(c, samples, n, theta, grad, loss);
     if (r != 0) return r < 0 ? m1_status(r) : M1_EDEVICE;
     return M1_OK;
+} catch (const std::exception &) {
+    return host_oom("m1_mlp_gradient: host allocation failed");
 }
 
 m1_status m1_opacity_eval(m1_ctx *c, long n, const double *rho, const double *T, double *kP, double *kR)
@@ -612,7 +642,7 @@ m1_status m1_max_dt(const m1_ctx *c, double cfl, double *dt)
 }
 
 m1_status m1_set_groups(m1_ctx *c, int m, const double *edges, const double *kP, const double *kR,
-                        double sigma)
+                        double sigma) try
 {
     if (!c) return fail(M1_EINVAL, "m1_set_groups: NULL context");
     if (c->bound) return fail(M1_ESTATE, "m1_set_groups: call before m1_bind_state");
@@ -637,6 +667,8 @@ m1_status m1_set_groups(m1_ctx *c, int m, const double *edges, const double *kP,
     }
     c->grp.sigma = sigma;
     return M1_OK;
+} catch (const std::exception &) {
+    return host_oom("m1_set_groups: host allocation failed");
 }
 
 // every fixed side has its ghost state
@@ -824,7 +856,7 @@ m1_status m1_sync(m1_ctx *c)
     return M1_OK;
 }
 
-m1_status m1_diagnostics(m1_ctx *c, m1_diag *out)
+m1_status m1_diagnostics(m1_ctx *c, m1_diag *out) try
 {
     if (!c || !out) return fail(M1_EINVAL, "m1_diagnostics: NULL argument");
     if (!c->bound) return fail(M1_ESTATE, "m1_diagnostics: no state bound");
@@ -846,6 +878,8 @@ m1_status m1_diagnostics(m1_ctx *c, m1_diag *out)
     out->max_f = v[6];
     for (int i = 0; i < 4; ++i) out->counters[i] = (long long)cnt[i];
     return M1_OK;
+} catch (const std::exception &) {
+    return host_oom("m1_diagnostics: host allocation failed");
 }
 
 const char *m1_last_error(void) { return g_err; }

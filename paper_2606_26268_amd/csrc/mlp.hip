@@ -566,6 +566,9 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
 
     const int nblk = cfg->batch / 64;
     const long n_eval_blocks = (cfg->n_eval + 255) / 256;
+    // host buffers first: a failed host allocation then leaves no device
+    // buffer behind
+    std::vector<float> hist(cfg->steps), em(2 * n_eval_blocks);
     float *buf = nullptr;
     const size_t nbuf = 3 * size_t(NP) + size_t(nblk) * NP + nblk + cfg->steps + 2 * n_eval_blocks;
     if (device_alloc(reinterpret_cast<void **>(&buf), nbuf * sizeof(float)) != hipSuccess) {
@@ -623,7 +626,6 @@ int mlp_train(m1_ctx *c, const m1_train_cfg *cfg, m1_train_report *rep)
                            cfg->samples + 2 * cfg->n_train, cfg->n_eval, c->op, evmax);
         e = hipGetLastError();
     }
-    std::vector<float> hist(cfg->steps), em(2 * n_eval_blocks);
     if (e == hipSuccess) e = hipMemcpyAsync(th.data(), theta, NP * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(hist.data(), loss_hist, cfg->steps * sizeof(float), hipMemcpyDeviceToHost, c->stream);
