@@ -477,3 +477,45 @@ def test_streaming_reads_change_no_bit(precision):
             s.close()
         for k in out[0]:
             assert np.array_equal(out[0][k], out[1][k]), (name, k)
+
+
+@pytest.mark.parametrize("shape", [(128, 128), (7, 5), (2, 2)])
+def test_table_lookup_matches_oracle_everywhere(orc, shape):
+    """The bilinear table on the GPU (m1_opacity_eval, FP64; it reads each
+    table cell's four node values from one record) against the oracle's
+    lookup: random points over and well beyond the axes (both clamps), every
+    node, and the midpoints of the first and last cells of every row; on the
+    benchmark's 128 x 128 nodes, a small ragged table and the smallest one."""
+    import torch
+    from paper_2606_26268_amd import m1
+    nr, nt = shape
+    tab = I.make_table(nr, nt)
+    p = I.make_uniform(I.CARTESIAN, (64, 1, 1), 1)
+    p.opacity = tab
+    s = m1.Solver(p, "p64")
+    rng = np.random.default_rng(11)
+    lr_axis = tab["lr0"] + (tab["lr1"] - tab["lr0"]) * np.arange(nr) / (nr - 1)
+    lt_axis = tab["lt0"] + (tab["lt1"] - tab["lt0"]) * np.arange(nt) / (nt - 1)
+    span_r, span_t = tab["lr1"] - tab["lr0"], tab["lt1"] - tab["lt0"]
+    lr = [rng.uniform(tab["lr0"] - 0.3 * span_r, tab["lr1"] + 0.3 * span_r, 4099)]
+    lt = [rng.uniform(tab["lt0"] - 0.3 * span_t, tab["lt1"] + 0.3 * span_t, 4099)]
+    LT, LR = np.meshgrid(lt_axis, lr_axis, indexing="ij")
+    lr.append(LR.ravel())
+    lt.append(LT.ravel())
+    mid_r = 0.5 * (lr_axis[[0, -2]] + lr_axis[[1, -1]])
+    MT, MR = np.meshgrid(lt_axis, mid_r, indexing="ij")
+    lr.append(MR.ravel())
+    lt.append(MT.ravel())
+    lr, lt = np.concatenate(lr), np.concatenate(lt)
+    rho, T = 10 ** (lr - tab["lr_off"]), 10 ** (lt - tab["lt_off"])
+    n = rho.size
+    kP = torch.empty(n, dtype=torch.float64, device="cuda")
+    kR = torch.empty_like(kP)
+    m1.m1_opacity_eval(s.ctx, n, torch.from_numpy(rho).to("cuda"), torch.from_numpy(T).to("cuda"), kP, kR)
+    s.sync()
+    s.close()
+    rP, rR = orc.Oracle(p).opacity(rho, T)
+    eP = np.abs(kP.cpu().numpy() / rP - 1).max()
+    eR = np.abs(kR.cpu().numpy() / rR - 1).max()
+    say(f"  table {nr}x{nt}: {n} points, max rel diff P {eP:.1e} R {eR:.1e}")
+    assert eP <= 1e-12 and eR <= 1e-12
