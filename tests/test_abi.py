@@ -43,3 +43,34 @@ def test_params_layout_matches_the_header():
     p = m1.m1_params_default(2.5)
     assert (p.c, p.a_rad, p.gamma, p.e_floor) == (2.5, 1.0, 5.0 / 3.0, 1e-30)
     assert (p.precision, p.recon, p.riemann, p.absorb_only, p.second_order) == (m1.M1_P64, 0, 0, 0, 0)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every structure of the binding has the size and field offsets that a
+    C compiler gives the header's declaration (gcc on the host; no GPU)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_2606_26268_amd import m1
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    structs = [getattr(m1, n) for n in ("m1_grid", "m1_params", "m1_fields", "m1_diag", "m1_mlp", "m1_train_cfg",
+                                        "m1_train_report")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "m1.h"', "int main(void) {"]
+    expect = []
+    for s in structs:
+        lines.append(f'    printf("%zu\\n", sizeof({s.__name__}));')
+        expect.append(C.sizeof(s))
+        for f in s._fields_:
+            lines.append(f'    printf("%zu\\n", offsetof({s.__name__}, {f[0]}));')
+            expect.append(getattr(s, f[0]).offset)
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    r = subprocess.run([gcc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == expect
